@@ -1,0 +1,276 @@
+/*
+ * qsv.h -- C ABI of libqsv.so, an MI355X (gfx950) state-vector simulator.
+ *
+ * The problem statement this library implements is Eq. 1 of the paper's
+ * introduction (arXiv:2203.08826): a gate acting on n_tar target qubits is a
+ * 2^n_tar x 2^n_tar complex matrix G(tau, tau') applied to the 2^n complex
+ * amplitudes psi(sigma_1..sigma_n) of an n-qubit state; the methodology
+ * section (Sec. 2) states the operator shape (state, gate matrix, target
+ * qubits; controlled gates; specialised X/Y/Z/SWAP operators; in-place
+ * update; measurement).
+ *
+ * Conventions used by every entry point:
+ *   - qubit q is bit q of the amplitude index (stride 2^q);
+ *   - a k-target gate matrix is row-major, 4^k entries, and targets[0] is the
+ *     most significant bit of its row/column index;
+ *   - a gate acts only on amplitudes whose control bits are all 1;
+ *   - states are contiguous device arrays of 2^n complex numbers, either
+ *     complex64 (interleaved float re, im) or complex128 (interleaved
+ *     double re, im), aligned to 16 bytes;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *
+ * Ownership and ordering: the caller owns every state and every output
+ * buffer; the library never allocates or frees them.  Host inputs (gate
+ * matrices, qubit lists, op lists) are consumed before the call returns, so
+ * the caller may free them immediately.  Work is queued asynchronously on
+ * `stream` and updates the state in place; outputs written to device memory
+ * are valid once the stream has reached them.  The library keeps no pointer
+ * to caller memory after returning.
+ *
+ * Errors: every argument is validated on the host before anything is queued.
+ * On error nothing is queued, the state is untouched and a negative QSV_ERR_*
+ * code is returned; qsv_last_error() then holds a message for the calling
+ * thread.  Faults of earlier asynchronous work surface at the next call that
+ * synchronises.  No C++ exception crosses this interface.  Calls are
+ * reentrant; calls on distinct streams are independent.
+ */
+#ifndef QSV_H
+#define QSV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QSV_ABI_VERSION 1
+
+/* Status codes. */
+enum {
+    QSV_OK = 0,
+    QSV_ERR_NULL = -1,        /* a required pointer is NULL */
+    QSV_ERR_DTYPE = -2,       /* dtype is not QSV_C64 / QSV_C128 */
+    QSV_ERR_NQUBITS = -3,     /* n < 1, n > QSV_MAX_QUBITS */
+    QSV_ERR_QUBIT_RANGE = -4, /* a qubit index is outside [0, n) */
+    QSV_ERR_QUBIT_DUP = -5,   /* a qubit repeats in targets + controls */
+    QSV_ERR_ARITY = -6,       /* k + c > n, or k / c above the limit of the call */
+    QSV_ERR_ALIGN = -7,       /* state pointer not 16-byte aligned */
+    QSV_ERR_UNSUPPORTED = -8, /* valid request this call does not implement */
+    QSV_ERR_HIP = -9,         /* the HIP runtime reported an error */
+    QSV_ERR_ARG = -10         /* another argument is out of its range */
+};
+
+/* State element types. */
+enum { QSV_C64 = 0, QSV_C128 = 1 };
+
+#define QSV_MAX_QUBITS 40
+#define QSV_MAX_TARGETS 6   /* k of a dense gate */
+#define QSV_MAX_CONTROLS 8  /* c of a controlled gate */
+
+/* ------------------------------------------------------------------ misc */
+
+int qsv_abi_version(void);
+const char *qsv_status_string(int status);
+/* Message of the last failing call on this thread ("" if none). */
+const char *qsv_last_error(void);
+
+/* Host-only validation of a gate's qubits (no HIP call; usable without a
+ * GPU): 1 <= n <= QSV_MAX_QUBITS, dtype valid, 0 <= k <= QSV_MAX_TARGETS,
+ * 0 <= c <= QSV_MAX_CONTROLS, k + c <= n, every index in [0, n), no repeats. */
+int qsv_validate(int n, int dtype, const int *targets, int k, const int *controls, int c);
+
+/* Host-only: group-index map used by every gate kernel (exposed for tests).
+ * Group g in [0, 2^(n - m)) maps to the index with a 0 inserted at each of
+ * the m sorted positions `bits` (ascending), i.e. the smallest member of the
+ * group.  Writes count indices starting at group `first` into out. */
+int qsv_group_index_host(int n, const int *bits, int m, uint64_t first, uint64_t count, uint64_t *out);
+
+/* ------------------------------------------------------------------ gates
+ * Eq. 1 for one gate, in place.  `gate` is host memory in the state's dtype
+ * (complex64 pairs of float, complex128 pairs of double), row-major 4^k
+ * entries.  The kernel chosen depends on the matrix: diagonal, monomial
+ * (permutation with phases: X, Y, SWAP, CNOT) and partly-identity matrices
+ * touch only the amplitudes they change (the sparsity the methodology section
+ * exploits for Pauli and controlled gates); others run the dense k-target
+ * kernel.  1 <= k <= QSV_MAX_TARGETS. */
+int qsv_apply_matrix(void *state, int n, int dtype, const void *gate,
+                     const int *targets, int k, const int *controls, int c, void *stream);
+
+/* Specialised gates (methodology section: Pauli X, Y, Z and SWAP operators;
+ * controlled gates).  Each touches only the amplitudes it changes.  X, SWAP
+ * and their controlled forms move amplitudes bit-exactly. */
+int qsv_apply_x(void *state, int n, int dtype, int target, const int *controls, int c, void *stream);
+int qsv_apply_y(void *state, int n, int dtype, int target, const int *controls, int c, void *stream);
+int qsv_apply_z(void *state, int n, int dtype, int target, const int *controls, int c, void *stream);
+int qsv_apply_swap(void *state, int n, int dtype, int t0, int t1, const int *controls, int c, void *stream);
+/* U1(phi) = diag(1, e^{i phi}); one control gives CU1, phi = pi gives CZ. */
+int qsv_apply_phase(void *state, int n, int dtype, int target, double phi,
+                    const int *controls, int c, void *stream);
+/* Diagonal gate: `diag` holds 2^k host values in the state's dtype, index
+ * order as for matrices; entries exactly equal to 1 are skipped. */
+int qsv_apply_diagonal(void *state, int n, int dtype, const void *diag,
+                       const int *targets, int k, const int *controls, int c, void *stream);
+/* fSim(theta, phi) on (t0, t1): |00> unchanged, [[cos, -i sin], [-i sin, cos]]
+ * on {|01>, |10>}, e^{-i phi} on |11> (t0 = most significant). */
+int qsv_apply_fsim(void *state, int n, int dtype, int t0, int t1, double theta, double phi, void *stream);
+
+/* ------------------------------------------------------------------ circuits
+ * A circuit is an array of qsv_gate.  Named kinds build their matrix from
+ * params; QSV_GATE_MATRIX and QSV_GATE_DIAG read `data` (host complex128,
+ * 4^k resp. 2^k entries).  CNOT, CZ and CU1 are X, Z and U1 with one entry in
+ * `controls`. */
+enum {
+    QSV_GATE_MATRIX = 0, QSV_GATE_H, QSV_GATE_X, QSV_GATE_Y, QSV_GATE_Z,
+    QSV_GATE_SX, QSV_GATE_SY, QSV_GATE_SW, QSV_GATE_RX, QSV_GATE_RY, QSV_GATE_RZ,
+    QSV_GATE_U1, QSV_GATE_SWAP, QSV_GATE_FSIM, QSV_GATE_DIAG,
+    QSV_GATE_KIND_COUNT
+};
+
+typedef struct qsv_gate {
+    int kind;                          /* QSV_GATE_* */
+    int k;                             /* number of targets */
+    int c;                             /* number of controls */
+    int targets[QSV_MAX_TARGETS];
+    int controls[QSV_MAX_CONTROLS];
+    double params[2];                  /* angles of named kinds */
+    const void *data;                  /* MATRIX / DIAG entries, complex128, host */
+} qsv_gate;
+
+/* Host-only: the complex128 target block of a gate (4^k entries) into out. */
+int qsv_gate_matrix(const qsv_gate *gate, double *out);
+
+/* Plans.  A plan turns a circuit into a sequence of kernel launches:
+ *   QSV_PLAN_PER_GATE  one launch per gate, no fusion;
+ *   QSV_PLAN_GREEDY    greedy fusion (Sec. 3.2 of the paper, extended to
+ *                      kmax <= 6): each gate joins the most recent of its
+ *                      qubits' last blocks while the union stays within kmax
+ *                      qubits; fused blocks with 4..6 qubits on complex64 run
+ *                      on the FP32 matrix-core kernel;
+ *   QSV_PLAN_PASSES    LDS-staged passes: consecutive gates whose non-diagonal
+ *                      targets fit one chunk of local qubits run in one HBM
+ *                      read + write of the state;
+ *   QSV_PLAN_LEARNED   the candidate plans above are scored by the MLP cost
+ *                      model loaded with qsv_cost_model_set and the cheapest
+ *                      is kept; without a model it is QSV_PLAN_GREEDY. */
+enum { QSV_PLAN_PER_GATE = 0, QSV_PLAN_GREEDY = 1, QSV_PLAN_PASSES = 2, QSV_PLAN_LEARNED = 3 };
+
+typedef struct qsv_plan_options {
+    int mode;          /* QSV_PLAN_* */
+    int kmax;          /* fusion width for QSV_PLAN_GREEDY, 1..6 (default 2) */
+    int local_bits;    /* chunk bits for QSV_PLAN_PASSES, 0 = library default */
+    int use_mfma;      /* 1: fused complex64 blocks of 4..6 qubits use MFMA */
+} qsv_plan_options;
+
+typedef struct qsv_plan qsv_plan;
+
+/* Statistics of a plan (host-side counts and the byte model of the launches). */
+typedef struct qsv_plan_stats {
+    int n_launches;        /* kernels per execution */
+    int n_gate_ops;        /* per-gate kernel launches */
+    int n_blocks;          /* fused dense blocks */
+    int n_mfma_blocks;     /* of which on MFMA */
+    int n_passes;          /* LDS passes */
+    int mode_used;         /* QSV_PLAN_* finally used (LEARNED resolves to another) */
+    double bytes;          /* algorithmic HBM bytes per execution */
+    double flops;          /* algorithmic flops per execution */
+    double predicted_s;    /* cost-model prediction, 0 if none */
+} qsv_plan_stats;
+
+/* Build a plan on the host (no HIP call unless mode = LEARNED with a model,
+ * which runs the MLP inference kernel on the current device).  The gates are
+ * copied; the caller may free them afterwards. */
+int qsv_plan_create(int n, int dtype, const qsv_gate *gates, int ngates,
+                    const qsv_plan_options *opts, qsv_plan **out);
+int qsv_plan_stats_get(const qsv_plan *plan, qsv_plan_stats *out);
+/* Greedy block of every gate (block ids in plan order) -- for tests; the plan
+ * must have been built with QSV_PLAN_GREEDY. */
+int qsv_plan_blocks(const qsv_plan *plan, int *block_of_gate, int ngates);
+/* Queue the whole plan on `stream`, updating `state` in place. */
+int qsv_plan_execute(const qsv_plan *plan, void *state, void *stream);
+void qsv_plan_destroy(qsv_plan *plan);
+
+/* Dense fused block on FP32 matrix cores (complex64 only): Y = G X with X
+ * the state viewed as 2^k x 2^(n-k) (rows = target bits).  `gate` is host
+ * complex64, 4^k entries; 4 <= k <= 6, no controls. */
+int qsv_apply_block(void *state, int n, int dtype, const void *gate, const int *targets, int k, void *stream);
+
+/* One LDS pass: every gate of `gates` is applied, in order, in a single HBM
+ * read + write.  `local_qubits` (nlocal of them, nlocal <= 13 for complex64,
+ * <= 12 for complex128, and containing qubits 0..2) are the chunk's qubits;
+ * every non-diagonal target must be local; controls and diagonal gates may
+ * be anywhere; SWAPs of two local qubits are permutations of the chunk. */
+int qsv_run_pass(void *state, int n, int dtype, const qsv_gate *gates, int ngates,
+                 const int *local_qubits, int nlocal, void *stream);
+
+/* ------------------------------------------------------------------ reductions
+ * Products are formed in the state's precision and accumulated in float64
+ * with a fixed-order tree, so results are reproducible run to run.  Outputs
+ * are device pointers. */
+
+/* Measurement probabilities of r qubits (methodology section: measurement):
+ * out[m] = sum of |psi_i|^2 over i whose measured bits spell m, with
+ * m = sum_j bit(i, qubits[j]) 2^(r-1-j).  out_dev holds 2^r doubles.
+ * 1 <= r <= n. */
+int qsv_probabilities(const void *state, int n, int dtype, const int *qubits, int r,
+                      double *out_dev, void *stream);
+/* out_dev[0] = <psi|psi>. */
+int qsv_norm2(const void *state, int n, int dtype, double *out_dev, void *stream);
+/* out_dev[0..1] = re, im of <a|b> = sum conj(a_i) b_i. */
+int qsv_inner(const void *a, const void *b, int n, int dtype, double *out_dev, void *stream);
+/* out_dev[0] = <psi| J sum_i Z_i Z_{i+1} + h sum_i X_i |psi> (open chain,
+ * or periodic when `periodic` != 0 and n > 2). */
+int qsv_expval_zz_x(const void *state, int n, int dtype, double J, double h, int periodic,
+                    double *out_dev, void *stream);
+/* out = (J sum Z_i Z_{i+1} + h sum X_i) psi, out a separate device state. */
+int qsv_apply_tfim(const void *state, void *out, int n, int dtype, double J, double h,
+                   int periodic, void *stream);
+
+/* ------------------------------------------------------------------ adjoint
+ * Adjoint-method gradient of E = <psi|H|psi> (Jones and Gacon,
+ * arXiv:2009.02823).  On entry psi holds U_L..U_1 psi_0 and lam holds H psi.
+ * Walking the gates backwards, for every rotation RX/RY/RZ (exp(-i theta P/2))
+ * the call computes Im <lam|P|psi> and then applies U^dagger to both vectors;
+ * on return psi holds psi_0 (up to rounding).  grad_dev receives one double
+ * per rotation, in circuit order.  The gates must be the ones that produced
+ * psi. */
+int qsv_adjoint_grad(void *psi, void *lam, int n, int dtype, const qsv_gate *gates, int ngates,
+                     double *grad_dev, void *stream);
+
+/* ------------------------------------------------------------------ MLP
+ * Fully connected network with ReLU hidden layers and a linear scalar
+ * output, FP32, on caller-owned device buffers.  Layer l has weights
+ * W_l [fan_in, fan_out] row-major and bias b_l [fan_out]; `params` is all
+ * layers concatenated (W_1, b_1, W_2, b_2, ...); `sizes` has nlayers + 1
+ * entries (input width first, 1 last); every width <= 256.
+ *   forward:  X [batch, sizes[0]] -> acts (sum of batch * sizes[1..] floats,
+ *             layer outputs after activation), pred [batch]
+ *   backward: gradient of mean((pred - target)^2) into grads (same layout as
+ *             params); `scratch` holds 2 * batch * max width floats
+ *   adam:     params -= lr * mhat / (sqrt(vhat) + eps), Adam step t >= 1 */
+int qsv_mlp_forward(const float *params, const int *sizes, int nlayers, const float *X, int batch,
+                    float *acts, float *pred, void *stream);
+int qsv_mlp_backward(const float *params, const int *sizes, int nlayers, const float *X, int batch,
+                     const float *acts, const float *pred, const float *target,
+                     float *grads, float *scratch, void *stream);
+int qsv_mlp_adam(float *params, const float *grads, float *m, float *v, int count, int t,
+                 float lr, float beta1, float beta2, float eps, void *stream);
+/* Number of floats of params for `sizes`. */
+int qsv_mlp_param_count(const int *sizes, int nlayers);
+
+/* Cost model used by QSV_PLAN_LEARNED: a copy of the parameters (host FP32,
+ * layout as above) and the feature normalisation (mean, scale per input).
+ * Passing nlayers = 0 removes the model. */
+int qsv_cost_model_set(const float *params, const int *sizes, int nlayers,
+                       const float *feat_mean, const float *feat_scale);
+/* Host-only: the feature vector (QSV_COST_FEATURES floats) of one candidate
+ * op, for training data.  variant: 0 = per-gate, 1 = dense block (VALU),
+ * 2 = MFMA block, 3 = LDS pass. */
+#define QSV_COST_FEATURES 12
+int qsv_cost_features(int n, int dtype, int variant, const int *qubits, int nq, int n_members,
+                      int is_diag, int is_perm, float *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QSV_H */

@@ -1,0 +1,333 @@
+// Per-gate kernels: Eq. 1 of the paper's introduction applied in place, one
+// launch per gate.
+//
+// Every kernel walks groups: a group is the set of amplitudes that differ
+// only in the gate's target bits, with every control bit set.  Group g is
+// turned into its smallest member by inserting a 0 at each sorted
+// target/control bit (the on-the-fly index generation of the methodology
+// section: i1 = ((g >> t) << (t + 1)) + (g & (2^t - 1)), generalised to
+// several bits), then OR-ing the control mask.  Only the members the gate
+// changes are read and written:
+//   k_dense : M members, M x M complex submatrix (general gates, fSim's
+//             3-member block, controlled gates);
+//   k_diag  : M members each multiplied by a factor (Z, U1/CU1, CZ, RZ,
+//             diagonal gates);
+//   k_perm  : M members each replaced by a (phase times) another member
+//             (X/CNOT, Y, SWAP): pure moves are bit-exact;
+//   k_low1  : one-target dense gates on a low qubit; each lane streams a
+//             contiguous 16-byte vector and partners inside the wave are
+//             exchanged with cross-lane shuffles, so every access stays a
+//             full contiguous vector.
+#include "qsv_internal.h"
+
+namespace qsv {
+
+#define QSV_MAX_BITS (QSV_MAX_TARGETS + QSV_MAX_CONTROLS)
+
+struct GroupArgs {
+    uint64_t lowmask[QSV_MAX_BITS];
+    uint64_t cmask;
+    uint64_t ngroups;
+    int m;
+};
+
+template <typename C, int M> struct DenseArgs {
+    uint64_t offs[M];
+    C mat[M <= 8 ? M * M : 1];   // inline for M <= 8
+    const C *dmat;               // device copy for M > 8
+};
+
+template <typename C, int M> struct DiagArgs {
+    uint64_t offs[M];
+    C fac[M];
+};
+
+template <typename C, int M> struct PermArgs {
+    uint64_t offs[M];
+    uint64_t src[M];
+    C fac[M];
+    uint64_t one;   // bit j set: member j is a pure move
+};
+
+__device__ inline uint64_t group_base(uint64_t g, const GroupArgs &ga) {
+    uint64_t i = g;
+#pragma unroll 1
+    for (int b = 0; b < ga.m; ++b) {
+        const uint64_t lo = i & ga.lowmask[b];
+        i = lo | ((i ^ lo) << 1);
+    }
+    return i | ga.cmask;
+}
+
+template <typename C, int M>
+__global__ void __launch_bounds__(256) k_dense(C *__restrict__ psi, GroupArgs ga, DenseArgs<C, M> da) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ga.ngroups; g += stride) {
+        const uint64_t base = group_base(g, ga);
+        C v[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) v[j] = psi[base + da.offs[j]];
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            C acc;
+            acc.x = 0;
+            acc.y = 0;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const C gm = (M <= 8) ? da.mat[r * M + j] : da.dmat[r * M + j];
+                acc = cfma(gm, v[j], acc);
+            }
+            psi[base + da.offs[r]] = acc;
+        }
+    }
+}
+
+template <typename C, int M>
+__global__ void __launch_bounds__(256) k_diag(C *__restrict__ psi, GroupArgs ga, DiagArgs<C, M> da) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ga.ngroups; g += stride) {
+        const uint64_t base = group_base(g, ga);
+        C v[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) v[j] = psi[base + da.offs[j]];
+#pragma unroll
+        for (int j = 0; j < M; ++j) psi[base + da.offs[j]] = cmul(da.fac[j], v[j]);
+    }
+}
+
+template <typename C, int M>
+__global__ void __launch_bounds__(256) k_perm(C *__restrict__ psi, GroupArgs ga, PermArgs<C, M> pa) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ga.ngroups; g += stride) {
+        const uint64_t base = group_base(g, ga);
+        C v[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) v[j] = psi[base + pa.src[j]];
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const C o = ((pa.one >> j) & 1) ? v[j] : cmul(pa.fac[j], v[j]);
+            psi[base + pa.offs[j]] = o;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ low-qubit path
+//
+// Lane L of a wave holds the VEC consecutive amplitudes starting at
+// index = (wave_base + L) * VEC.  Target bit t < log2(VEC) pairs inside the
+// lane's vector; log2(VEC) <= t < log2(VEC) + 6 pairs with lane L ^ (1 << (t -
+// log2 VEC)), reached with a cross-lane shuffle.  Each lane computes only its
+// own outputs: out(b) = G[b][0] * a0 + G[b][1] * a1 with (a0, a1) the pair.
+template <typename C> struct Low1Args {
+    C g00, g01, g10, g11;
+    uint64_t cmask;
+    uint64_t nvec;      // number of VEC-vectors in the state
+    int t;              // target bit
+};
+
+template <typename C> __device__ inline C shfl_xor_c(C v, int lanemask) {
+    C r;
+    r.x = __shfl_xor(v.x, lanemask, 64);
+    r.y = __shfl_xor(v.y, lanemask, 64);
+    return r;
+}
+
+template <typename C, int VEC>
+__global__ void __launch_bounds__(256) k_low1(C *__restrict__ psi, Low1Args<C> a) {
+    constexpr int LV = (VEC == 1) ? 0 : (VEC == 2) ? 1 : 2;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    // every lane of a wave runs the same number of iterations: nvec is a
+    // multiple of 64 (the state has at least 64 * VEC amplitudes)
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.nvec; w += stride) {
+        const uint64_t i0 = w * VEC;
+        C v[VEC];
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) v[j] = psi[i0 + j];
+        C o[VEC];
+        if (a.t < LV) {
+            const int tb = 1 << a.t;
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                const int b = (j & tb) ? 1 : 0;
+                const C p0 = b ? v[j ^ tb] : v[j];
+                const C p1 = b ? v[j] : v[j ^ tb];
+                C acc = cmul(b ? a.g10 : a.g00, p0);
+                acc = cfma(b ? a.g11 : a.g01, p1, acc);
+                o[j] = acc;
+            }
+        } else {
+            const int lm = 1 << (a.t - LV);
+            const int b = (threadIdx.x & lm) ? 1 : 0;
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                const C q = shfl_xor_c(v[j], lm);
+                const C p0 = b ? q : v[j];
+                const C p1 = b ? v[j] : q;
+                C acc = cmul(b ? a.g10 : a.g00, p0);
+                acc = cfma(b ? a.g11 : a.g01, p1, acc);
+                o[j] = acc;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const bool on = ((i0 + j) & a.cmask) == a.cmask;
+            psi[i0 + j] = on ? o[j] : v[j];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launch
+
+static int grid_for(uint64_t items, int threads) {
+    uint64_t blocks = (items + threads - 1) / threads;
+    const uint64_t cap = (uint64_t)device_sm_count() * 64;   // grid-stride beyond this
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    return (int)blocks;
+}
+
+static GroupArgs make_group_args(const GateAnalysis &a) {
+    GroupArgs ga;
+    memset(&ga, 0, sizeof(ga));
+    ga.m = (int)a.sorted_bits.size();
+    for (int i = 0; i < ga.m; ++i) ga.lowmask[i] = (1ull << a.sorted_bits[i]) - 1ull;
+    ga.cmask = a.cmask;
+    ga.ngroups = 1ull << (a.n - ga.m);
+    return ga;
+}
+
+template <typename C> static C to_c(const double *z) {
+    C r;
+    r.x = (decltype(r.x))z[0];
+    r.y = (decltype(r.y))z[1];
+    return r;
+}
+
+template <typename C, int M>
+static void launch_dense_m(C *psi, const GateAnalysis &a, const GroupArgs &ga, const C *dmat, hipStream_t s) {
+    DenseArgs<C, M> da;
+    memset(&da, 0, sizeof(da));
+    for (int j = 0; j < M; ++j) da.offs[j] = a.offs[j];
+    if (M <= 8)
+        for (int j = 0; j < M * M; ++j) da.mat[j] = to_c<C>(&a.mat[2 * j]);
+    da.dmat = dmat;
+    hipLaunchKernelGGL((k_dense<C, M>), dim3(grid_for(ga.ngroups, 256)), dim3(256), 0, s, psi, ga, da);
+}
+
+template <typename C, int M>
+static void launch_diag_m(C *psi, const GateAnalysis &a, const GroupArgs &ga, hipStream_t s) {
+    DiagArgs<C, M> da;
+    memset(&da, 0, sizeof(da));
+    for (int j = 0; j < M; ++j) {
+        da.offs[j] = a.offs[j];
+        da.fac[j] = to_c<C>(&a.mat[2 * j]);
+    }
+    hipLaunchKernelGGL((k_diag<C, M>), dim3(grid_for(ga.ngroups, 256)), dim3(256), 0, s, psi, ga, da);
+}
+
+template <typename C, int M>
+static void launch_perm_m(C *psi, const GateAnalysis &a, const GroupArgs &ga, hipStream_t s) {
+    PermArgs<C, M> pa;
+    memset(&pa, 0, sizeof(pa));
+    for (int j = 0; j < M; ++j) {
+        pa.offs[j] = a.offs[j];
+        pa.src[j] = a.offs[a.perm_src[j]];
+        pa.fac[j] = to_c<C>(&a.mat[2 * j]);
+        if (a.perm_one[j]) pa.one |= 1ull << j;
+    }
+    hipLaunchKernelGGL((k_perm<C, M>), dim3(grid_for(ga.ngroups, 256)), dim3(256), 0, s, psi, ga, pa);
+}
+
+// Low-qubit path for a one-target dense gate whose target is below the
+// lane-exchange span: the lane vector is 16 bytes (2 complex64 or 1 complex128)
+// and partners up to 64 vectors away are reached by shuffles.
+template <typename C, int VEC>
+static bool try_low1(C *psi, const GateAnalysis &a, hipStream_t s) {
+    constexpr int LV = (VEC == 1) ? 0 : (VEC == 2) ? 1 : 2;
+    if (a.cls != GC_DENSE || a.k != 1 || a.members.size() != 2) return false;
+    const int t = __builtin_ctzll(a.offs[0] ^ a.offs[1]);
+    if (t >= LV + 6) return false;
+    if (a.n < LV + 6) return false;   // need whole waves of vectors
+    Low1Args<C> la;
+    la.g00 = to_c<C>(&a.mat[0]);
+    la.g01 = to_c<C>(&a.mat[2]);
+    la.g10 = to_c<C>(&a.mat[4]);
+    la.g11 = to_c<C>(&a.mat[6]);
+    la.cmask = a.cmask;
+    la.nvec = (1ull << a.n) / VEC;
+    la.t = t;
+    hipLaunchKernelGGL((k_low1<C, VEC>), dim3(grid_for(la.nvec, 256)), dim3(256), 0, s, psi, la);
+    return true;
+}
+
+template <typename R>
+static int launch_gate_t(void *state, const GateAnalysis &a, hipStream_t s) {
+    typedef typename cplx_of<R>::type C;
+    C *psi = (C *)state;
+    const int M = (int)a.members.size();
+    if (M == 0) return QSV_OK;   // identity
+    const GroupArgs ga = make_group_args(a);
+    if (a.cls == GC_DENSE && try_low1<C, sizeof(R) == 4 ? 2 : 1>(psi, a, s)) {
+        QSV_HIP_CHECK(hipGetLastError());
+        return QSV_OK;
+    }
+    StagingSlot slot;
+    const C *dmat = nullptr;
+    if (a.cls == GC_DENSE && M > 8) {
+        const size_t bytes = (size_t)M * M * sizeof(C);
+        int st = staging_acquire(bytes, &slot);
+        if (st) return st;
+        C *h = (C *)slot.host;
+        for (int j = 0; j < M * M; ++j) h[j] = to_c<C>(&a.mat[2 * j]);
+        st = staging_upload(slot, bytes, s);
+        if (st) return st;
+        dmat = (const C *)slot.dev;
+    }
+    switch (a.cls) {
+    case GC_DIAG:
+        switch (M) {
+        case 1: launch_diag_m<C, 1>(psi, a, ga, s); break;
+        case 2: launch_diag_m<C, 2>(psi, a, ga, s); break;
+        case 4: launch_diag_m<C, 4>(psi, a, ga, s); break;
+        case 8: launch_diag_m<C, 8>(psi, a, ga, s); break;
+        case 16: launch_diag_m<C, 16>(psi, a, ga, s); break;
+        case 32: launch_diag_m<C, 32>(psi, a, ga, s); break;
+        case 64: launch_diag_m<C, 64>(psi, a, ga, s); break;
+        default: return fail(QSV_ERR_ARG, "internal: diagonal member count not padded");
+        }
+        break;
+    case GC_PERM:
+        switch (M) {
+        case 2: launch_perm_m<C, 2>(psi, a, ga, s); break;
+        case 4: launch_perm_m<C, 4>(psi, a, ga, s); break;
+        case 8: launch_perm_m<C, 8>(psi, a, ga, s); break;
+        case 16: launch_perm_m<C, 16>(psi, a, ga, s); break;
+        case 32: launch_perm_m<C, 32>(psi, a, ga, s); break;
+        case 64: launch_perm_m<C, 64>(psi, a, ga, s); break;
+        default: return fail(QSV_ERR_ARG, "internal: permutation member count not padded");
+        }
+        break;
+    default:
+        switch (M) {
+        case 2: launch_dense_m<C, 2>(psi, a, ga, dmat, s); break;
+        case 3: launch_dense_m<C, 3>(psi, a, ga, dmat, s); break;
+        case 4: launch_dense_m<C, 4>(psi, a, ga, dmat, s); break;
+        case 8: launch_dense_m<C, 8>(psi, a, ga, dmat, s); break;
+        case 16: launch_dense_m<C, 16>(psi, a, ga, dmat, s); break;
+        case 32: launch_dense_m<C, 32>(psi, a, ga, dmat, s); break;
+        case 64: launch_dense_m<C, 64>(psi, a, ga, dmat, s); break;
+        default: return fail(QSV_ERR_ARG, "internal: dense member count not padded");
+        }
+        break;
+    }
+    hipError_t e = hipGetLastError();
+    if (dmat) staging_release(slot, s);
+    if (e != hipSuccess) return hip_fail(e, "gate kernel launch");
+    return QSV_OK;
+}
+
+int launch_gate(void *state, int dtype, const GateAnalysis &a, hipStream_t s) {
+    return dtype == QSV_C64 ? launch_gate_t<float>(state, a, s) : launch_gate_t<double>(state, a, s);
+}
+
+}  // namespace qsv

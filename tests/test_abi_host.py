@@ -1,0 +1,98 @@
+"""Host-side checks of libqsv.so that need no GPU: symbols, validation,
+index generation and the library's own gate matrices."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2203_08826_amd as qsv
+import workloads as W
+from oracle import gates as OG
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "qsv.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qsv_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = qsv.load()
+    syms = _declared_symbols()
+    assert len(syms) >= 30
+    for s in syms:
+        assert hasattr(lib, s), s
+        assert s in qsv._abi.SIGNATURES, s
+    assert qsv.qsv_abi_version() == 1
+
+
+def test_validation_codes():
+    ok = qsv.qsv_validate(5, qsv.QSV_C64, [0, 3], [4])
+    assert ok == 0
+    assert qsv.qsv_validate(0, 0, [0], []) == -3
+    assert qsv.qsv_validate(41, 0, [0], []) == -3
+    assert qsv.qsv_validate(5, 2, [0], []) == -2
+    assert qsv.qsv_validate(5, 0, [5], []) == -4
+    assert qsv.qsv_validate(5, 0, [-1], []) == -4
+    assert qsv.qsv_validate(5, 0, [1, 1], []) == -5
+    assert qsv.qsv_validate(5, 0, [1], [1]) == -5
+    assert qsv.qsv_validate(3, 0, [0, 1], [2, 3]) == -6
+    assert qsv.qsv_validate(10, 0, list(range(7)), []) == -6
+    assert qsv.qsv_status_string(-5) == "repeated qubit"
+
+
+def test_errors_leave_no_launch_and_raise():
+    # validation runs before any HIP call, so it works without a GPU
+    import ctypes
+    lib = qsv.load()
+    t = (ctypes.c_int * 1)(7)
+    st = lib.qsv_apply_x(ctypes.c_void_p(16), 5, 0, 7, None, 0, None)
+    assert st == -4 and "outside" in qsv.qsv_last_error()
+    st = lib.qsv_apply_x(None, 5, 0, 1, None, 0, None)
+    assert st == -1
+    st = lib.qsv_apply_x(ctypes.c_void_p(8), 5, 0, 1, None, 0, None)
+    assert st == -7
+    del t
+
+
+@pytest.mark.parametrize("n", [1, 3, 7, 12])
+def test_group_index_is_a_bijection_onto_disjoint_groups(n):
+    rng = np.random.default_rng(n)
+    for m in range(0, min(n, 4) + 1):
+        bits = sorted(int(b) for b in rng.permutation(n)[:m])
+        base = qsv.qsv_group_index_host(n, bits, 0, 1 << (n - m))
+        mask = sum(1 << b for b in bits)
+        assert np.all((base & np.uint64(mask)) == 0)
+        # groups {base + sub-mask of bits} tile [0, 2^n) exactly once
+        seen = np.zeros(1 << n, dtype=np.int64)
+        subs = [sum(1 << bits[j] for j in range(m) if (s >> j) & 1) for s in range(1 << m)]
+        for s in subs:
+            np.add.at(seen, (base + np.uint64(s)).astype(np.int64), 1)
+        assert np.all(seen == 1)
+        # the paper's one-qubit formula i1 = ((g >> t) << (t + 1)) + (g & (2^t - 1))
+        if m == 1:
+            g = np.arange(1 << (n - 1), dtype=np.uint64)
+            t = np.uint64(bits[0])
+            want = ((g >> t) << (t + np.uint64(1))) + (g & ((np.uint64(1) << t) - np.uint64(1)))
+            assert np.array_equal(base, want)
+
+
+def test_library_gate_matrices_match_oracle():
+    rng = np.random.default_rng(0)
+    names = ["H", "X", "Y", "Z", "SX", "SY", "SW", "RX", "RY", "RZ", "U1", "CNOT", "CZ", "CU1", "SWAP", "FSIM"]
+    for name in names:
+        for _ in range(3):
+            k = 2 if name in ("SWAP", "FSIM") else 1
+            g = W.gate(name, list(range(k)), [], list(rng.uniform(0, 2 * np.pi, size=2)))
+            got = qsv.qsv_gate_matrix(g)
+            want = OG.target_matrix(dict(g, params=g["params"][:1] if name not in ("FSIM",) else g["params"]))
+            assert np.max(np.abs(got - want)) <= 1e-15, name
+    u = W.random_unitary(3, rng)
+    g = {"name": "UNITARY", "targets": [0, 1, 2], "controls": [], "matrix": u}
+    assert np.array_equal(qsv.qsv_gate_matrix(g), u)
+    d = W.random_phases(2, rng)
+    g = {"name": "DIAG", "targets": [0, 1], "controls": [], "diag": d}
+    assert np.array_equal(qsv.qsv_gate_matrix(g), np.diag(d))

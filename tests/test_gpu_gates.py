@@ -1,0 +1,167 @@
+"""GPU parity of the per-gate kernels against the oracle (through the C ABI).
+
+Tolerances (max-abs over amplitudes of normalised states): 1e-12 for
+complex128, 1e-5 for complex64.  Pure moves (X, CNOT, SWAP) must be
+bit-exact.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import paper_2203_08826_amd as qsv
+import workloads as W
+from oracle import gates as OG
+from oracle import statevec as S
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c64": 1e-5, "c128": 1e-12}
+
+
+def _dev(psi, dt):
+    import torch
+    t = torch.complex64 if dt == "c64" else torch.complex128
+    return torch.from_numpy(np.asarray(psi, dtype=np.complex128)).to(t).cuda().contiguous()
+
+
+def _host(t):
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def _apply_dict(state, g):
+    name, tg, cs = g["name"], g["targets"], g.get("controls", [])
+    p = g.get("params", [])
+    if name in ("X", "CNOT"):
+        qsv.qsv_apply_x(state, tg[0], cs)
+    elif name == "Y":
+        qsv.qsv_apply_y(state, tg[0], cs)
+    elif name in ("Z", "CZ"):
+        qsv.qsv_apply_z(state, tg[0], cs)
+    elif name == "SWAP":
+        qsv.qsv_apply_swap(state, tg[0], tg[1], cs)
+    elif name in ("U1", "CU1"):
+        qsv.qsv_apply_phase(state, tg[0], p[0], cs)
+    elif name == "FSIM" and not cs:
+        qsv.qsv_apply_fsim(state, tg[0], tg[1], p[0], p[1])
+    elif name == "DIAG":
+        qsv.qsv_apply_diagonal(state, g["diag"], tg, cs)
+    else:
+        qsv.qsv_apply_matrix(state, OG.target_matrix(g), tg, cs)
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("n", [3, 7, 13])
+def test_random_gates_match_oracle(gpu, dt, n):
+    circ = W.random_circuit(n, 120, seed=n, kmax=min(n, 6), max_controls=2)
+    psi0 = W.random_state(n, 1)
+    st = _dev(psi0, dt)
+    want = psi0.copy()
+    for i, g in enumerate(circ):
+        _apply_dict(st, g)
+        want = S.apply_gate(want, g)
+        if i % 20 == 19 or i == len(circ) - 1:
+            err = np.max(np.abs(_host(st) - want))
+            assert err <= TOL[dt] * (4 if dt == "c64" else 1), (i, g["name"], err)
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_dense_k_up_to_6_with_controls(gpu, dt):
+    n = 14
+    rng = np.random.default_rng(5)
+    for k in range(1, 7):
+        for c in (0, 1, 2):
+            qs = [int(q) for q in rng.permutation(n)[:k + c]]
+            u = W.random_unitary(k, rng)
+            psi0 = W.random_state(n, k * 10 + c)
+            st = _dev(psi0, dt)
+            qsv.qsv_apply_matrix(st, u, qs[:k], qs[k:])
+            want = S.apply_matrix(psi0, u, qs[:k], qs[k:])
+            assert np.max(np.abs(_host(st) - want)) <= TOL[dt], (k, c)
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_low_qubit_shuffle_path(gpu, dt):
+    n = 12
+    rng = np.random.default_rng(2)
+    for t in range(0, 9):
+        for cs in ([], [11], [t + 1]):
+            u = W.random_unitary(1, rng)
+            psi0 = W.random_state(n, t)
+            st = _dev(psi0, dt)
+            qsv.qsv_apply_matrix(st, u, [t], cs)
+            want = S.apply_matrix(psi0, u, [t], cs)
+            assert np.max(np.abs(_host(st) - want)) <= TOL[dt], (t, cs)
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_moves_are_bit_exact(gpu, dt):
+    import torch
+    n = 11
+    psi0 = W.random_state(n, 3)
+    st = _dev(psi0, dt)
+    ref = st.clone()
+    idx = np.arange(1 << n)
+    qsv.qsv_apply_x(st, 4)
+    qsv.qsv_apply_x(st, 0, [7, 2])
+    qsv.qsv_apply_swap(st, 1, 9)
+    qsv.qsv_apply_swap(st, 3, 10, [5])
+    src = idx.copy()
+    # compose the index permutation on the host: out[i] = in[src[i]]
+    def perm_x(t, cs):
+        on = np.all([(idx >> c) & 1 for c in cs], axis=0) if cs else np.ones_like(idx, bool)
+        return np.where(on, idx ^ (1 << t), idx)
+
+    def perm_swap(a, b, cs):
+        on = np.all([(idx >> c) & 1 for c in cs], axis=0) if cs else np.ones_like(idx, bool)
+        ba, bb = (idx >> a) & 1, (idx >> b) & 1
+        sw = idx & ~((1 << a) | (1 << b)) | (bb << a) | (ba << b)
+        return np.where(on, sw, idx)
+
+    for p in (perm_x(4, []), perm_x(0, [7, 2]), perm_swap(1, 9, []), perm_swap(3, 10, [5])):
+        src = src[p]
+    want = ref.cpu()[torch.from_numpy(src)]
+    assert torch.equal(st.cpu(), want)
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_qft20_random_gaussian(gpu, dt):
+    """20-qubit QFT on the seeded random Gaussian state, against the oracle
+    and numpy's inverse FFT."""
+    n = 20
+    psi0 = W.random_state(n, 0)
+    st = _dev(psi0, dt)
+    for g in W.qft(n):
+        _apply_dict(st, g)
+    got = _host(st)
+    ref = np.fft.ifft(psi0, norm="ortho")
+    assert np.max(np.abs(got - ref)) <= TOL[dt]
+    if dt == "c128":
+        want = S.run_circuit(psi0, W.qft(n))
+        assert np.max(np.abs(got - want)) <= 1e-12
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_ghz(gpu, dt):
+    n = 16
+    st = _dev(S.basis_state(n, 0), dt)
+    for g in W.ghz(n):
+        _apply_dict(st, g)
+    got = _host(st)
+    want = np.zeros(1 << n, complex)
+    want[0] = want[-1] = 1 / math.sqrt(2)
+    assert np.max(np.abs(got - want)) <= TOL[dt]
+
+
+def test_errors_raise_and_leave_state(gpu):
+    import torch
+    st = _dev(W.random_state(6, 0), "c64")
+    ref = st.clone()
+    with pytest.raises(qsv.QsvError):
+        qsv.qsv_apply_x(st, 6)
+    with pytest.raises(qsv.QsvError):
+        qsv.qsv_apply_swap(st, 2, 2)
+    with pytest.raises(qsv.QsvError):
+        qsv.qsv_apply_matrix(st, np.eye(2), [1], [1])
+    torch.cuda.synchronize()
+    assert torch.equal(st, ref)
