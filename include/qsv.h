@@ -188,6 +188,11 @@ int qsv_plan_stats_get(const qsv_plan *plan, qsv_plan_stats *out);
 int qsv_plan_blocks(const qsv_plan *plan, int *block_of_gate, int ngates);
 /* Queue the whole plan on `stream`, updating `state` in place. */
 int qsv_plan_execute(const qsv_plan *plan, void *state, void *stream);
+/* Queue ops [first, first + count) of the plan only (for per-op timing). */
+int qsv_plan_execute_ops(const qsv_plan *plan, void *state, int first, int count, void *stream);
+/* Kind (0 = gate kernel, 1 = MFMA block, 2 = LDS pass), algorithmic HBM
+ * bytes and flops of op `index`; any output pointer may be NULL. */
+int qsv_plan_op_info(const qsv_plan *plan, int index, int *kind, double *bytes, double *flops);
 void qsv_plan_destroy(qsv_plan *plan);
 
 /* Dense fused block on FP32 matrix cores (complex64 only): Y = G X with X

@@ -256,6 +256,20 @@ def qsv_plan_execute(plan, state, stream=None):
     check("qsv_plan_execute", load().qsv_plan_execute(plan._h, p, _stream(stream)))
 
 
+def qsv_plan_execute_ops(plan, state, first, count, stream=None):
+    p, n, dt = _state(state)
+    check("qsv_plan_execute_ops", load().qsv_plan_execute_ops(plan._h, p, int(first), int(count), _stream(stream)))
+
+
+def qsv_plan_op_info(plan, index):
+    kind = ctypes.c_int()
+    b = ctypes.c_double()
+    f = ctypes.c_double()
+    check("qsv_plan_op_info", load().qsv_plan_op_info(plan._h, int(index), ctypes.byref(kind), ctypes.byref(b),
+                                                      ctypes.byref(f)))
+    return {"kind": kind.value, "bytes": b.value, "flops": f.value}
+
+
 def qsv_plan_destroy(plan):
     if plan._h:
         load().qsv_plan_destroy(plan._h)

@@ -1,0 +1,384 @@
+// LDS-staged multi-gate pass: several gates per HBM read + write of the state.
+//
+// Gate fusion (Sec. 3.2 of the paper) multiplies gate matrices to cut the
+// number of sweeps over the state; a pass goes further and keeps a chunk of
+// 2^L amplitudes on chip while a whole run of gates is applied to it.  The
+// chunk is the set of amplitudes sharing every non-local bit.  Thread t of
+// the 256-thread workgroup holds 2^RB of them in registers (L = RB + 8):
+//   - one- and two-qubit gates whose targets are register bits run in
+//     registers (in-place Eq. 1 on pairs / quads);
+//   - an EXCHANGE rewrites the chunk through LDS with another assignment of
+//     local bits to register / thread bits (bank-swizzled layout);
+//   - diagonal gates on any bits run as PHASE ops: every unit-modulus
+//     diagonal gate is a sum of phase terms theta * prod(bits), evaluated in
+//     exact fixed-point turns and split into parts that depend on the chunk,
+//     the thread and the register index;
+//   - controls on non-local bits are per-chunk predicates;
+//   - SWAPs of two local bits are relabelings of local positions, applied by
+//     the store's bit map at no cost.
+// Global loads and stores keep the lowest global bits on lanes, so every
+// wave instruction touches contiguous runs of at least 512 bytes.
+#include "plan_internal.h"
+
+namespace qsv {
+
+constexpr int PT = 256;
+
+__device__ __forceinline__ uint32_t lds_swizzle(uint32_t l) {
+    return l ^ (((l >> 4) ^ (l >> 8) ^ (l >> 12)) & 15u);
+}
+
+template <typename C>
+__device__ __forceinline__ C cmadd(C a, C g, C b, C h) {
+    // g * a + h * b
+    C r;
+    r.x = g.x * a.x - g.y * a.y + h.x * b.x - h.y * b.y;
+    r.y = g.x * a.y + g.y * a.x + h.x * b.y + h.y * b.x;
+    return r;
+}
+
+template <typename C, typename R, int NR, int I>
+__device__ __forceinline__ void g1(C *v, const R *m, uint32_t cj, bool tok) {
+    C g00, g01, g10, g11;
+    g00.x = m[0]; g00.y = m[1]; g01.x = m[2]; g01.y = m[3];
+    g10.x = m[4]; g10.y = m[5]; g11.x = m[6]; g11.y = m[7];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        if ((j >> I) & 1) continue;
+        const int j1 = j | (1 << I);
+        const bool ok = tok && (((uint32_t)j & cj) == cj);
+        const C a = v[j], b = v[j1];
+        const C o0 = cmadd(a, g00, b, g01);
+        const C o1 = cmadd(a, g10, b, g11);
+        v[j] = ok ? o0 : a;
+        v[j1] = ok ? o1 : b;
+    }
+}
+
+template <typename C, typename R, int NR, int I>
+__device__ __forceinline__ void g1r(C *v, const R *m, uint32_t cj, bool tok) {
+    const R g00 = m[0], g01 = m[1], g10 = m[2], g11 = m[3];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        if ((j >> I) & 1) continue;
+        const int j1 = j | (1 << I);
+        const bool ok = tok && (((uint32_t)j & cj) == cj);
+        const C a = v[j], b = v[j1];
+        C o0, o1;
+        o0.x = g00 * a.x + g01 * b.x;
+        o0.y = g00 * a.y + g01 * b.y;
+        o1.x = g10 * a.x + g11 * b.x;
+        o1.y = g10 * a.y + g11 * b.y;
+        v[j] = ok ? o0 : a;
+        v[j1] = ok ? o1 : b;
+    }
+}
+
+template <typename C, typename R, int NR, int I1, int I2>
+__device__ __forceinline__ void g2(C *v, const R *m, uint32_t cj, bool tok) {
+    C g[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        g[e].x = m[2 * e];
+        g[e].y = m[2 * e + 1];
+    }
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        if (((j >> I1) & 1) || ((j >> I2) & 1)) continue;
+        const int jj[4] = {j, j | (1 << I2), j | (1 << I1), j | (1 << I1) | (1 << I2)};
+        const bool ok = tok && (((uint32_t)j & cj) == cj);
+        C a[4], o[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = v[jj[r]];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            C acc = cmul(g[4 * r], a[0]);
+            acc = cfma(g[4 * r + 1], a[1], acc);
+            acc = cfma(g[4 * r + 2], a[2], acc);
+            acc = cfma(g[4 * r + 3], a[3], acc);
+            o[r] = acc;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[jj[r]] = ok ? o[r] : a[r];
+    }
+}
+
+template <typename C, typename R, int NR, int RB>
+__device__ __forceinline__ void dispatch_g1(int a, bool real, C *v, const R *m, uint32_t cj, bool tok) {
+#define QSV_G1(I)                                                   \
+    case I:                                                         \
+        if constexpr (I < RB) {                                     \
+            if (real) g1r<C, R, NR, I>(v, m, cj, tok);              \
+            else g1<C, R, NR, I>(v, m, cj, tok);                    \
+        }                                                           \
+        break;
+    switch (a) {
+        QSV_G1(0) QSV_G1(1) QSV_G1(2) QSV_G1(3) QSV_G1(4)
+    }
+#undef QSV_G1
+}
+
+template <typename C, typename R, int NR, int RB>
+__device__ __forceinline__ void dispatch_g2(int a, int b, C *v, const R *m, uint32_t cj, bool tok) {
+#define QSV_G2(I1, I2)                                              \
+    case I1 * 8 + I2:                                               \
+        if constexpr (I1 < RB) g2<C, R, NR, I1, I2>(v, m, cj, tok); \
+        break;
+    switch (a * 8 + b) {
+        QSV_G2(1, 0) QSV_G2(2, 0) QSV_G2(2, 1) QSV_G2(3, 0) QSV_G2(3, 1)
+        QSV_G2(3, 2) QSV_G2(4, 0) QSV_G2(4, 1) QSV_G2(4, 2) QSV_G2(4, 3)
+    }
+#undef QSV_G2
+}
+
+// phase = theta(fixed-point turns) -> multiply by e^{2 pi i phase}
+__device__ __forceinline__ float2 rot(float2 v, uint64_t ph) {
+    const float x = (float)(int32_t)(uint32_t)(ph >> 32) * 2.3283064365386963e-10f;   // turns in [-1/2, 1/2)
+    float s, c;
+    sincospif(2.0f * x, &s, &c);
+    float2 r;
+    r.x = v.x * c - v.y * s;
+    r.y = v.x * s + v.y * c;
+    return r;
+}
+__device__ __forceinline__ double2 rot(double2 v, uint64_t ph) {
+    const double x = (double)(int64_t)ph * 5.421010862427522e-20;   // 2^-64
+    double s, c;
+    sincospi(2.0 * x, &s, &c);
+    double2 r;
+    r.x = v.x * c - v.y * s;
+    r.y = v.x * s + v.y * c;
+    return r;
+}
+
+template <typename C, int NR, int RB>
+__device__ __forceinline__ void phase_op(C *v, const PassOpDev &op, const PassTermDev *terms, uint32_t t,
+                                         uint64_t base) {
+    constexpr int NQ = RB * (RB - 1) / 2;
+    auto sum_group = [&](int g) -> uint64_t {
+        uint64_t s = 0;
+        const int e = op.grp[g + 1];
+        for (int k = op.grp[g]; k < e; ++k) {
+            const PassTermDev tm = terms[k];
+            const bool ok = ((t & tm.mt) == tm.mt) && ((base & tm.mn) == tm.mn);
+            s += ok ? tm.theta : 0ull;
+        }
+        return s;
+    };
+    const uint64_t c0 = sum_group(0);
+    uint64_t lin[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) lin[i] = sum_group(1 + i);
+    uint64_t quad[NQ > 0 ? NQ : 1];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) quad[q] = sum_group(1 + RB + q);
+    const int gen_b = op.grp[1 + RB + NQ], gen_e = op.grp[2 + RB + NQ];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        uint64_t ph = c0;
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+            if ((j >> i) & 1) ph += lin[i];
+#pragma unroll
+        for (int i1 = 1; i1 < RB; ++i1)
+#pragma unroll
+            for (int i2 = 0; i2 < i1; ++i2)
+                if (((j >> i1) & 1) && ((j >> i2) & 1)) ph += quad[i1 * (i1 - 1) / 2 + i2];
+        for (int k = gen_b; k < gen_e; ++k) {
+            const PassTermDev tm = terms[k];
+            const bool ok = ((t & tm.mt) == tm.mt) && ((base & tm.mn) == tm.mn) && (((uint32_t)j & tm.mj) == tm.mj);
+            ph += ok ? tm.theta : 0ull;
+        }
+        v[j] = rot(v[j], ph);
+    }
+}
+
+template <typename R, int RB>
+__global__ void __launch_bounds__(PT) k_pass(typename cplx_of<R>::type *__restrict__ psi, const uint8_t *__restrict__ prog,
+                                             uint64_t nchunks) {
+    typedef typename cplx_of<R>::type C;
+    constexpr int NR = 1 << RB;
+    constexpr int L = RB + PASS_THREAD_BITS;
+    __shared__ C lds[1 << L];
+
+    const PassHeaderDev *H = (const PassHeaderDev *)prog;
+    const PassPartition *parts = (const PassPartition *)(prog + H->off_part);
+    const PassOpDev *ops = (const PassOpDev *)(prog + H->off_ops);
+    const R *pool = (const R *)(prog + H->off_pool);
+    const PassTermDev *terms = (const PassTermDev *)(prog + H->off_terms);
+    const uint32_t t = threadIdx.x;
+    const int nops = H->nops;
+
+    for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        uint64_t base = c;
+#pragma unroll
+        for (int b = 0; b < L; ++b) {
+            const uint64_t lo = base & H->lowmask[b];
+            base = lo | ((base ^ lo) << 1);
+        }
+        C v[NR];
+        int cur = H->load_part;
+        {
+            const PassPartition &P = parts[cur];
+            uint64_t gt = base;
+#pragma unroll
+            for (int u = 0; u < PASS_THREAD_BITS; ++u)
+                if ((t >> u) & 1) gt |= 1ull << H->in_pos[P.thr_l[u]];
+            uint64_t gr[RB];
+#pragma unroll
+            for (int i = 0; i < RB; ++i) gr[i] = 1ull << H->in_pos[P.reg_l[i]];
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                uint64_t g = gt;
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+                    if ((j >> i) & 1) g |= gr[i];
+                v[j] = psi[g];
+            }
+        }
+        for (int o = 0; o < nops; ++o) {
+            const PassOpDev &op = ops[o];
+            const bool tok = ((t & op.ct) == op.ct) && ((base & op.cn) == op.cn);
+            switch (op.kind) {
+            case POP_G1: dispatch_g1<C, R, NR, RB>(op.a, false, v, pool + op.mat, op.cj, tok); break;
+            case POP_G1R: dispatch_g1<C, R, NR, RB>(op.a, true, v, pool + op.mat, op.cj, tok); break;
+            case POP_G2: dispatch_g2<C, R, NR, RB>(op.a, op.b, v, pool + op.mat, op.cj, tok); break;
+            case POP_PHASE: phase_op<C, NR, RB>(v, op, terms, t, base); break;
+            case POP_EXCHANGE: {
+                const PassPartition &P = parts[cur];
+                const PassPartition &Q = parts[op.a];
+                uint32_t lt = 0, lq = 0;
+#pragma unroll
+                for (int u = 0; u < PASS_THREAD_BITS; ++u) {
+                    if ((t >> u) & 1) {
+                        lt |= 1u << P.thr_l[u];
+                        lq |= 1u << Q.thr_l[u];
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < NR; ++j) {
+                    uint32_t l = lt;
+#pragma unroll
+                    for (int i = 0; i < RB; ++i)
+                        if ((j >> i) & 1) l |= 1u << P.reg_l[i];
+                    lds[lds_swizzle(l)] = v[j];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < NR; ++j) {
+                    uint32_t l = lq;
+#pragma unroll
+                    for (int i = 0; i < RB; ++i)
+                        if ((j >> i) & 1) l |= 1u << Q.reg_l[i];
+                    v[j] = lds[lds_swizzle(l)];
+                }
+                cur = op.a;
+                break;
+            }
+            default: break;
+            }
+        }
+        {
+            const PassPartition &P = parts[cur];
+            uint64_t gt = base;
+#pragma unroll
+            for (int u = 0; u < PASS_THREAD_BITS; ++u)
+                if ((t >> u) & 1) gt |= 1ull << H->out_pos[P.thr_l[u]];
+            uint64_t gr[RB];
+#pragma unroll
+            for (int i = 0; i < RB; ++i) gr[i] = 1ull << H->out_pos[P.reg_l[i]];
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                uint64_t g = gt;
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+                    if ((j >> i) & 1) g |= gr[i];
+                psi[g] = v[j];
+            }
+        }
+    }
+}
+
+void PassProgram::serialise() {
+    PassHeaderDev h;
+    std::memset(&h, 0, sizeof(h));
+    h.L = L;
+    h.nops = (int)ops.size();
+    h.npart = (int)parts.size();
+    h.load_part = load_part;
+    for (int l = 0; l < L; ++l) {
+        h.in_pos[l] = local_sorted[l];
+        h.out_pos[l] = out_pos[l];
+        h.lowmask[l] = (1ull << local_sorted[l]) - 1ull;
+    }
+    auto align = [](size_t x) { return (x + 15) & ~(size_t)15; };
+    size_t off = align(sizeof(PassHeaderDev));
+    h.off_part = (int)off;
+    off = align(off + parts.size() * sizeof(PassPartition));
+    h.off_ops = (int)off;
+    off = align(off + ops.size() * sizeof(PassOpDev));
+    h.off_pool = (int)off;
+    off = align(off + pool.size() * sizeof(double));   // room for the widest real type
+    h.off_terms = (int)off;
+    off = align(off + terms.size() * sizeof(PassTermDev));
+    h.total_bytes = (int)off;
+    blob.assign(off, 0);
+    std::memcpy(blob.data(), &h, sizeof(h));
+    if (!parts.empty()) std::memcpy(blob.data() + h.off_part, parts.data(), parts.size() * sizeof(PassPartition));
+    if (!ops.empty()) std::memcpy(blob.data() + h.off_ops, ops.data(), ops.size() * sizeof(PassOpDev));
+    if (!terms.empty()) std::memcpy(blob.data() + h.off_terms, terms.data(), terms.size() * sizeof(PassTermDev));
+    // the pool is written per dtype at launch time (float or double)
+}
+
+template <typename R, int RB>
+static void launch_k_pass(void *state, const uint8_t *dprog, uint64_t nchunks, hipStream_t s) {
+    uint64_t g = nchunks;
+    if (g > (1ull << 20)) g = 1ull << 20;
+    hipLaunchKernelGGL((k_pass<R, RB>), dim3((unsigned)g), dim3(PT), 0, s, (typename cplx_of<R>::type *)state, dprog,
+                       nchunks);
+}
+
+int launch_pass_program(void *state, int n, int dtype, const PassProgram &prog, hipStream_t s) {
+    const size_t bytes = prog.blob.size();
+    if (bytes > staging_slot_bytes()) return fail(QSV_ERR_UNSUPPORTED, "pass program larger than a staging slot");
+    StagingSlot slot;
+    int st = staging_acquire(bytes, &slot);
+    if (st) return st;
+    std::memcpy(slot.host, prog.blob.data(), bytes);
+    const PassHeaderDev *h = (const PassHeaderDev *)prog.blob.data();
+    if (dtype == QSV_C64) {
+        float *pool = (float *)((char *)slot.host + h->off_pool);
+        for (size_t i = 0; i < prog.pool.size(); ++i) pool[i] = (float)prog.pool[i];
+    } else {
+        double *pool = (double *)((char *)slot.host + h->off_pool);
+        for (size_t i = 0; i < prog.pool.size(); ++i) pool[i] = prog.pool[i];
+    }
+    if ((st = staging_upload(slot, bytes, s))) return st;
+    const uint64_t nchunks = 1ull << (n - prog.L);
+    const uint8_t *d = (const uint8_t *)slot.dev;
+    if (dtype == QSV_C64) {
+        switch (prog.RB) {
+        case 1: launch_k_pass<float, 1>(state, d, nchunks, s); break;
+        case 2: launch_k_pass<float, 2>(state, d, nchunks, s); break;
+        case 3: launch_k_pass<float, 3>(state, d, nchunks, s); break;
+        case 4: launch_k_pass<float, 4>(state, d, nchunks, s); break;
+        case 5: launch_k_pass<float, 5>(state, d, nchunks, s); break;
+        default: staging_release(slot, s); return fail(QSV_ERR_ARG, "internal: bad register bits");
+        }
+    } else {
+        switch (prog.RB) {
+        case 1: launch_k_pass<double, 1>(state, d, nchunks, s); break;
+        case 2: launch_k_pass<double, 2>(state, d, nchunks, s); break;
+        case 3: launch_k_pass<double, 3>(state, d, nchunks, s); break;
+        case 4: launch_k_pass<double, 4>(state, d, nchunks, s); break;
+        default: staging_release(slot, s); return fail(QSV_ERR_ARG, "internal: bad register bits");
+        }
+    }
+    hipError_t e = hipGetLastError();
+    staging_release(slot, s);
+    if (e != hipSuccess) return hip_fail(e, "pass kernel launch");
+    return QSV_OK;
+}
+
+}  // namespace qsv

@@ -1,0 +1,502 @@
+// Host planner for LDS-staged passes (see pass_kernel.hip for the device
+// side).  Splits a circuit into runs of gates that fit one chunk of local
+// qubits, reorders diagonal phase terms as late as they commute, assigns
+// register/thread bits per op and emits the pass programs.
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "plan_internal.h"
+
+namespace qsv {
+
+namespace {
+
+constexpr int LANE_BITS = 6;
+
+// One gate seen by the pass planner.
+struct PGate {
+    enum Kind { PHASE, NONDIAG, SWAP, OTHER } kind = OTHER;
+    int gi = -1;
+    std::vector<int> targets;      // global bits, targets[0] = MSB of the matrix index
+    std::vector<int> controls;
+    std::vector<double> M;         // complex128 target block (NONDIAG)
+    // PHASE: terms over global bits (mask, fixed-point turns)
+    std::vector<std::pair<uint64_t, uint64_t>> terms;
+};
+
+uint64_t turns_fixed(double re, double im) {
+    double t = std::atan2(im, re) / (2.0 * M_PI);   // (-1/2, 1/2]
+    if (t >= 0.5) t -= 1.0;
+    const long double scaled = (long double)t * 18446744073709551616.0L;
+    return (uint64_t)(int64_t)std::llroundl(scaled);
+}
+
+int classify(const qsv_gate &g, PGate &pg) {
+    std::vector<double> G;
+    int st = gate_target_matrix(g, G);
+    if (st) return st;
+    pg.targets.assign(g.targets, g.targets + g.k);
+    pg.controls.assign(g.controls, g.controls + g.c);
+    const int d = 1 << g.k;
+    bool diag = true;
+    for (int r = 0; r < d && diag; ++r)
+        for (int c = 0; c < d; ++c)
+            if (r != c && (G[2 * (r * d + c)] != 0.0 || G[2 * (r * d + c) + 1] != 0.0)) { diag = false; break; }
+    if (diag) {
+        bool unit = true;
+        std::vector<uint64_t> alpha(d);
+        for (int t = 0; t < d; ++t) {
+            const double re = G[2 * (t * d + t)], im = G[2 * (t * d + t) + 1];
+            if (std::fabs(std::hypot(re, im) - 1.0) > 1e-14) unit = false;
+            alpha[t] = turns_fixed(re, im);
+        }
+        if (!unit) {
+            pg.kind = PGate::OTHER;
+            return QSV_OK;
+        }
+        // Moebius inversion: theta_S = sum_{T subset S} (-1)^{|S|-|T|} alpha_T
+        uint64_t cm = 0;
+        for (int q : pg.controls) cm |= 1ull << q;
+        for (int S = 0; S < d; ++S) {
+            uint64_t th = 0;
+            for (int T = S;; T = (T - 1) & S) {
+                if ((__builtin_popcount(S) - __builtin_popcount(T)) & 1) th -= alpha[T];
+                else th += alpha[T];
+                if (T == 0) break;
+            }
+            if (th == 0) continue;
+            uint64_t mask = cm;
+            for (int j = 0; j < g.k; ++j)
+                if ((S >> (g.k - 1 - j)) & 1) mask |= 1ull << g.targets[j];
+            pg.terms.push_back({mask, th});
+        }
+        pg.kind = PGate::PHASE;
+        return QSV_OK;
+    }
+    if (g.kind == QSV_GATE_SWAP && g.c == 0) {
+        pg.kind = PGate::SWAP;
+        return QSV_OK;
+    }
+    if (g.k <= 2) {
+        pg.kind = PGate::NONDIAG;
+        pg.M = G;
+        return QSV_OK;
+    }
+    pg.kind = PGate::OTHER;
+    return QSV_OK;
+}
+
+// ---------------------------------------------------------------- one pass
+
+struct LOp {                        // an op in local-position space
+    bool phase = false;
+    std::vector<int> lt;            // NONDIAG: target local positions (lt[0] = MSB)
+    uint32_t lc = 0;                // local control positions
+    uint64_t gc = 0;                // non-local control bits
+    std::vector<double> M;
+    std::vector<std::pair<uint64_t, std::pair<uint32_t, uint64_t>>> terms;   // PHASE: (theta, (lmask, gmask))
+};
+
+struct Part {
+    std::vector<int> reg;   // local positions of register bits
+    std::vector<int> thr;   // local positions of thread bits (lanes first)
+};
+
+bool same_set(std::vector<int> a, std::vector<int> b) {
+    std::sort(a.begin(), a.end());
+    std::sort(b.begin(), b.end());
+    return a == b;
+}
+
+// Fill a partition: registers get `want` (first RB distinct), lanes get the
+// lowest remaining positions by `rank`, then the wave bits.
+Part make_part(int L, int RB, const std::vector<int> &want, const std::vector<int> &rank_order) {
+    Part p;
+    std::vector<int> used(L, 0);
+    for (int l : want) {
+        if ((int)p.reg.size() == RB) break;
+        if (!used[l]) {
+            used[l] = 1;
+            p.reg.push_back(l);
+        }
+    }
+    // registers still free: take the highest-ranked positions so lanes keep the low ones
+    for (int i = (int)rank_order.size() - 1; i >= 0 && (int)p.reg.size() < RB; --i) {
+        const int l = rank_order[i];
+        if (!used[l]) {
+            used[l] = 1;
+            p.reg.push_back(l);
+        }
+    }
+    for (int l : rank_order)
+        if (!used[l]) p.thr.push_back(l);
+    return p;
+}
+
+int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> &local, int RB,
+                 PassProgram &prog) {
+    const int L = (int)local.size();
+    prog.L = L;
+    prog.RB = RB;
+    prog.local_sorted = local;
+    std::sort(prog.local_sorted.begin(), prog.local_sorted.end());
+    int lpos[QSV_MAX_QUBITS];
+    for (int q = 0; q < QSV_MAX_QUBITS; ++q) lpos[q] = -1;
+    for (int l = 0; l < L; ++l) lpos[prog.local_sorted[l]] = l;
+    int cur_l[QSV_MAX_QUBITS];   // local position holding logical qubit q (SWAP relabelings)
+    for (int q = 0; q < QSV_MAX_QUBITS; ++q) cur_l[q] = lpos[q];
+
+    // 1. resolve gates to local-position ops; defer phase terms while they commute
+    std::vector<LOp> ops;
+    LOp pending;
+    pending.phase = true;
+    auto flush = [&](uint32_t blocking, bool all) {
+        LOp out;
+        out.phase = true;
+        std::vector<std::pair<uint64_t, std::pair<uint32_t, uint64_t>>> keep;
+        for (auto &t : pending.terms) {
+            if (all || (t.second.first & blocking)) out.terms.push_back(t);
+            else keep.push_back(t);
+        }
+        pending.terms.swap(keep);
+        if (!out.terms.empty()) ops.push_back(std::move(out));
+    };
+    for (const PGate &g : gates) {
+        switch (g.kind) {
+        case PGate::PHASE:
+            for (auto &t : g.terms) {
+                uint32_t lm = 0;
+                uint64_t gm = 0;
+                for (int q = 0; q < n; ++q) {
+                    if (!((t.first >> q) & 1)) continue;
+                    if (cur_l[q] >= 0) lm |= 1u << cur_l[q];
+                    else gm |= 1ull << q;
+                }
+                pending.terms.push_back({t.second, {lm, gm}});
+            }
+            break;
+        case PGate::SWAP: {
+            const int a = g.targets[0], b = g.targets[1];
+            if (cur_l[a] < 0 || cur_l[b] < 0) return fail(QSV_ERR_ARG, "internal: SWAP on a non-local qubit in a pass");
+            std::swap(cur_l[a], cur_l[b]);
+            break;
+        }
+        case PGate::NONDIAG: {
+            LOp op;
+            uint32_t tmask = 0;
+            for (int q : g.targets) {
+                if (cur_l[q] < 0) return fail(QSV_ERR_ARG, "internal: pass target is not local");
+                op.lt.push_back(cur_l[q]);
+                tmask |= 1u << cur_l[q];
+            }
+            for (int q : g.controls) {
+                if (cur_l[q] >= 0) op.lc |= 1u << cur_l[q];
+                else op.gc |= 1ull << q;
+            }
+            op.M = g.M;
+            flush(tmask, false);
+            ops.push_back(std::move(op));
+            break;
+        }
+        default: return fail(QSV_ERR_ARG, "internal: gate kind not allowed in a pass");
+        }
+    }
+    flush(0, true);
+
+    // store map: local position l holds logical qubit q with cur_l[q] == l
+    prog.out_pos.assign(L, -1);
+    for (int q = 0; q < n; ++q)
+        if (cur_l[q] >= 0) prog.out_pos[cur_l[q]] = q;
+
+    // rank orders: local positions by global bit at load / at store
+    std::vector<int> in_rank(L), out_rank(L);
+    for (int l = 0; l < L; ++l) in_rank[l] = l;
+    for (int l = 0; l < L; ++l) out_rank[l] = l;
+    std::sort(out_rank.begin(), out_rank.end(), [&](int a, int b) { return prog.out_pos[a] < prog.out_pos[b]; });
+
+    // 2. partitions.  Load: lanes on the 6 lowest positions; registers on the
+    // first targets among the others.
+    std::vector<std::vector<int>> need;   // per op: targets (empty for PHASE)
+    for (auto &op : ops) need.push_back(op.phase ? std::vector<int>() : op.lt);
+    auto upcoming = [&](size_t from, const std::vector<int> &forbid) {
+        std::vector<int> w;
+        for (size_t o = from; o < ops.size() && (int)w.size() < RB; ++o)
+            for (int l : need[o])
+                if (std::find(w.begin(), w.end(), l) == w.end() &&
+                    std::find(forbid.begin(), forbid.end(), l) == forbid.end())
+                    w.push_back(l);
+        return w;
+    };
+    const int lanes = std::min(LANE_BITS, L - RB);
+    std::vector<int> low_in(in_rank.begin(), in_rank.begin() + lanes);
+    std::vector<Part> parts;
+    Part cur = make_part(L, RB, upcoming(0, low_in), in_rank);
+    parts.push_back(cur);
+    prog.load_part = 0;
+
+    prog.ops.clear();
+    prog.pool.clear();
+    prog.terms.clear();
+    auto reg_index = [&](const Part &p, int l) {
+        for (int i = 0; i < (int)p.reg.size(); ++i)
+            if (p.reg[i] == l) return i;
+        return -1;
+    };
+    auto thr_index = [&](const Part &p, int l) {
+        for (int u = 0; u < (int)p.thr.size(); ++u)
+            if (p.thr[u] == l) return u;
+        return -1;
+    };
+    auto emit_exchange = [&](const Part &np) {
+        parts.push_back(np);
+        PassOpDev d;
+        std::memset(&d, 0, sizeof(d));
+        d.kind = POP_EXCHANGE;
+        d.a = (int)parts.size() - 1;
+        prog.ops.push_back(d);
+        cur = np;
+    };
+    for (size_t o = 0; o < ops.size(); ++o) {
+        const LOp &op = ops[o];
+        PassOpDev d;
+        std::memset(&d, 0, sizeof(d));
+        if (!op.phase) {
+            bool ok = true;
+            for (int l : op.lt)
+                if (reg_index(cur, l) < 0) ok = false;
+            if (!ok) {
+                std::vector<int> w = upcoming(o, {});
+                // keep current lanes when possible, so LDS patterns stay regular
+                emit_exchange(make_part(L, RB, w, in_rank));
+            }
+            for (int l = 0; l < L; ++l) {
+                if (!((op.lc >> l) & 1)) continue;
+                const int i = reg_index(cur, l);
+                if (i >= 0) d.cj |= 1u << i;
+                else d.ct |= 1u << thr_index(cur, l);
+            }
+            d.cn = op.gc;
+            d.mat = (int)prog.pool.size();
+            if (op.lt.size() == 1) {
+                d.a = reg_index(cur, op.lt[0]);
+                bool real = true;
+                for (int e = 0; e < 4; ++e)
+                    if (op.M[2 * e + 1] != 0.0) real = false;
+                if (real) {
+                    d.kind = POP_G1R;
+                    for (int e = 0; e < 4; ++e) prog.pool.push_back(op.M[2 * e]);
+                } else {
+                    d.kind = POP_G1;
+                    for (int e = 0; e < 8; ++e) prog.pool.push_back(op.M[e]);
+                }
+            } else {
+                d.kind = POP_G2;
+                int i0 = reg_index(cur, op.lt[0]), i1 = reg_index(cur, op.lt[1]);
+                bool swapq = false;
+                if (i0 < i1) {
+                    std::swap(i0, i1);
+                    swapq = true;
+                }
+                d.a = i0;
+                d.b = i1;
+                auto sw = [&](int x) { return swapq ? (((x & 1) << 1) | ((x >> 1) & 1)) : x; };
+                for (int r = 0; r < 4; ++r)
+                    for (int c = 0; c < 4; ++c) {
+                        const int e = sw(r) * 4 + sw(c);
+                        prog.pool.push_back(op.M[2 * e]);
+                        prog.pool.push_back(op.M[2 * e + 1]);
+                    }
+            }
+        } else {
+            d.kind = POP_PHASE;
+            // group the terms by the register bits they need under `cur`
+            const int NQ = RB * (RB - 1) / 2;
+            const int ngroups = 1 + RB + NQ + 1;
+            std::vector<std::vector<PassTermDev>> groups(ngroups);
+            for (auto &t : op.terms) {
+                PassTermDev td;
+                std::memset(&td, 0, sizeof(td));
+                td.theta = t.first;
+                td.mn = t.second.second;
+                std::vector<int> regs;
+                for (int l = 0; l < L; ++l) {
+                    if (!((t.second.first >> l) & 1)) continue;
+                    const int i = reg_index(cur, l);
+                    if (i >= 0) {
+                        regs.push_back(i);
+                        td.mj |= 1u << i;
+                    } else {
+                        td.mt |= 1u << thr_index(cur, l);
+                    }
+                }
+                int gidx;
+                if (regs.empty()) gidx = 0;
+                else if (regs.size() == 1) gidx = 1 + regs[0];
+                else if (regs.size() == 2) {
+                    const int a = std::max(regs[0], regs[1]), b = std::min(regs[0], regs[1]);
+                    gidx = 1 + RB + a * (a - 1) / 2 + b;
+                } else gidx = ngroups - 1;
+                groups[gidx].push_back(td);
+            }
+            int k = (int)prog.terms.size();
+            for (int g = 0; g < ngroups; ++g) {
+                d.grp[g] = k;
+                for (auto &td : groups[g]) prog.terms.push_back(td);
+                k = (int)prog.terms.size();
+            }
+            d.grp[ngroups] = k;
+        }
+        prog.ops.push_back(d);
+    }
+    // store: lanes must be the 6 positions with the lowest output bits
+    std::vector<int> low_out(out_rank.begin(), out_rank.begin() + lanes);
+    std::vector<int> cur_lanes(cur.thr.begin(), cur.thr.begin() + lanes);
+    if (!same_set(cur_lanes, low_out)) {
+        // registers: current registers that are not store lanes, then the highest outputs
+        std::vector<int> w;
+        for (int l : cur.reg)
+            if (std::find(low_out.begin(), low_out.end(), l) == low_out.end()) w.push_back(l);
+        emit_exchange(make_part(L, RB, w, out_rank));
+    }
+    prog.parts.clear();
+    for (auto &p : parts) {
+        PassPartition pp;
+        std::memset(&pp, 0, sizeof(pp));
+        for (int i = 0; i < RB; ++i) pp.reg_l[i] = p.reg[i];
+        for (int u = 0; u < PASS_THREAD_BITS; ++u) pp.thr_l[u] = p.thr[u];
+        prog.parts.push_back(pp);
+    }
+    prog.n_gates = (int)gates.size();
+    prog.serialise();
+    return QSV_OK;
+}
+
+}  // namespace
+
+int pass_register_bits(int n, int dtype, int local_bits) {
+    const int rb_max = dtype == QSV_C64 ? 5 : 4;
+    int L = local_bits > 0 ? local_bits : rb_max + PASS_THREAD_BITS;
+    if (L > n) L = n;
+    const int RB = L - PASS_THREAD_BITS;
+    if (RB < 1 || RB > rb_max) return -1;
+    return RB;
+}
+
+int build_passes(qsv_plan *p, int local_bits) {
+    const int n = p->n;
+    const int RB = pass_register_bits(n, p->dtype, local_bits);
+    if (local_bits > 0 && RB < 0) return fail(QSV_ERR_ARG, "local_bits outside the supported range");
+    if (RB < 0) {
+        // too few qubits for a chunk: per-gate launches
+        for (const auto &g : p->gates) {
+            int st = plan_add_gate_op(p, g);
+            if (st) return st;
+        }
+        return QSV_OK;
+    }
+    const int L = RB + PASS_THREAD_BITS;
+    const int lanes = std::min(LANE_BITS, L - RB);
+    std::vector<PGate> pgs(p->gates.size());
+    for (size_t i = 0; i < p->gates.size(); ++i) {
+        int st = classify(p->gates[i], pgs[i]);
+        if (st) return st;
+        pgs[i].gi = (int)i;
+    }
+    std::vector<PGate> run;
+    uint64_t S = 0;   // local set (global bits) of the open pass
+    auto reset_local = [&]() {
+        S = 0;
+        for (int q = 0; q < lanes; ++q) S |= 1ull << q;
+    };
+    auto close = [&]() -> int {
+        if (run.empty()) return QSV_OK;
+        // fill the local set with the lowest missing bits
+        for (int q = 0; q < n && __builtin_popcountll(S) < L; ++q) S |= 1ull << q;
+        std::vector<int> local;
+        for (int q = 0; q < n; ++q)
+            if ((S >> q) & 1) local.push_back(q);
+        auto prog = std::make_shared<PassProgram>();
+        int st = compile_pass(n, run, local, RB, *prog);
+        if (st) return st;
+        PlanOp op;
+        op.kind = PlanOp::PASS;
+        op.pass = prog;
+        const double s = p->dtype == QSV_C64 ? 8.0 : 16.0;
+        op.bytes = 2.0 * std::ldexp(1.0, n) * s;
+        double fl = 0;
+        for (auto &g : run) fl += g.kind == PGate::NONDIAG ? (g.targets.size() == 1 ? 8.0 : 16.0) * std::ldexp(1.0, n)
+                                                            : 0.0;
+        op.flops = fl;
+        p->ops.push_back(std::move(op));
+        p->stats.n_passes++;
+        run.clear();
+        reset_local();
+        return QSV_OK;
+    };
+    reset_local();
+    for (size_t i = 0; i < pgs.size(); ++i) {
+        PGate &g = pgs[i];
+        if (g.kind == PGate::OTHER) {
+            int st = close();
+            if (!st) st = plan_add_gate_op(p, p->gates[i]);
+            if (st) return st;
+            continue;
+        }
+        uint64_t need = 0;
+        if (g.kind == PGate::NONDIAG || g.kind == PGate::SWAP)
+            for (int q : g.targets) need |= 1ull << q;
+        if (__builtin_popcountll(S | need) > L) {
+            int st = close();
+            if (st) return st;
+        }
+        S |= need;
+        run.push_back(g);
+    }
+    return close();
+}
+
+int build_single_pass(int n, int dtype, const std::vector<qsv_gate> &gates, const std::vector<int> &local,
+                      PassProgram &out) {
+    const int L = (int)local.size();
+    const int RB = pass_register_bits(n, dtype, L);
+    if (RB < 0 || L != RB + PASS_THREAD_BITS) return fail(QSV_ERR_ARG, "nlocal must be in [9, 13] (complex64) or [9, 12] (complex128) and <= n");
+    uint64_t S = 0;
+    for (int q : local) {
+        if (q < 0 || q >= n) return fail(QSV_ERR_QUBIT_RANGE, "local qubit out of range");
+        if ((S >> q) & 1) return fail(QSV_ERR_QUBIT_DUP, "local qubit repeats");
+        S |= 1ull << q;
+    }
+    for (int q = 0; q < 3; ++q)
+        if (!((S >> q) & 1)) return fail(QSV_ERR_ARG, "local qubits must contain qubits 0, 1 and 2");
+    std::vector<PGate> pgs(gates.size());
+    for (size_t i = 0; i < gates.size(); ++i) {
+        int st = classify(gates[i], pgs[i]);
+        if (st) return st;
+        if (pgs[i].kind == PGate::OTHER)
+            return fail(QSV_ERR_UNSUPPORTED, "gate " + std::to_string(i) + " cannot run in a pass (dense k > 2 or non-unitary diagonal)");
+        if (pgs[i].kind != PGate::PHASE)
+            for (int q : pgs[i].targets)
+                if (!((S >> q) & 1)) return fail(QSV_ERR_ARG, "gate " + std::to_string(i) + " targets a non-local qubit");
+    }
+    return compile_pass(n, pgs, local, RB, out);
+}
+
+}  // namespace qsv
+
+using namespace qsv;
+
+extern "C" int qsv_run_pass(void *state, int n, int dtype, const qsv_gate *gates, int ngates, const int *local_qubits,
+                            int nlocal, void *stream) {
+    int st = validate_common(n, dtype, nullptr, 0, nullptr, 0);
+    if (st) return st;
+    if (!state || !local_qubits || (ngates > 0 && !gates)) return fail(QSV_ERR_NULL, "NULL argument");
+    if (((uintptr_t)state & 15) != 0) return fail(QSV_ERR_ALIGN, "state must be 16-byte aligned");
+    std::vector<qsv_gate> gs(gates, gates + ngates);
+    for (auto &g : gs)
+        if ((st = validate_common(n, dtype, g.targets, g.k, g.controls, g.c))) return st;
+    PassProgram prog;
+    std::vector<int> local(local_qubits, local_qubits + nlocal);
+    if ((st = build_single_pass(n, dtype, gs, local, prog))) return st;
+    return launch_pass_program(state, n, dtype, prog, (hipStream_t)stream);
+}
