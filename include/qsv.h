@@ -193,6 +193,10 @@ int qsv_plan_execute_ops(const qsv_plan *plan, void *state, int first, int count
 /* Kind (0 = gate kernel, 1 = MFMA block, 2 = LDS pass), algorithmic HBM
  * bytes and flops of op `index`; any output pointer may be NULL. */
 int qsv_plan_op_info(const qsv_plan *plan, int index, int *kind, double *bytes, double *flops);
+/* Host-only: copy the serialised program of LDS-pass op `index` (layout in
+ * plan_internal.h: header, partitions, ops, real pool, phase terms; the pool
+ * is stored as doubles) into buf (cap bytes); *size receives the length. */
+int qsv_plan_op_program(const qsv_plan *plan, int index, void *buf, size_t cap, size_t *size);
 void qsv_plan_destroy(qsv_plan *plan);
 
 /* Dense fused block on FP32 matrix cores (complex64 only): Y = G X with X

@@ -270,6 +270,15 @@ def qsv_plan_op_info(plan, index):
     return {"kind": kind.value, "bytes": b.value, "flops": f.value}
 
 
+def qsv_plan_op_program(plan, index):
+    """Host-only: serialised LDS-pass program of op `index` as bytes."""
+    size = ctypes.c_size_t()
+    check("qsv_plan_op_program", load().qsv_plan_op_program(plan._h, int(index), None, 0, ctypes.byref(size)))
+    buf = ctypes.create_string_buffer(size.value)
+    check("qsv_plan_op_program", load().qsv_plan_op_program(plan._h, int(index), buf, size.value, ctypes.byref(size)))
+    return buf.raw[:size.value]
+
+
 def qsv_plan_destroy(plan):
     if plan._h:
         load().qsv_plan_destroy(plan._h)

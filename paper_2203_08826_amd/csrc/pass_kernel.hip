@@ -103,16 +103,23 @@ __device__ __forceinline__ void g2(C *v, const R *m, uint32_t cj, bool tok) {
     }
 }
 
+template <typename C, typename R, int NR, int RB, int I>
+__device__ __forceinline__ void pre_phase(C *v, const PassOpDev &op, const PassTermDev *terms, const R *pool,
+                                          uint32_t t, uint64_t base);
+
 template <typename C, typename R, int NR, int RB>
-__device__ __forceinline__ void dispatch_g1(int a, bool real, C *v, const R *m, uint32_t cj, bool tok) {
-#define QSV_G1(I)                                                   \
-    case I:                                                         \
-        if constexpr (I < RB) {                                     \
-            if (real) g1r<C, R, NR, I>(v, m, cj, tok);              \
-            else g1<C, R, NR, I>(v, m, cj, tok);                    \
-        }                                                           \
+__device__ __forceinline__ void dispatch_g1(const PassOpDev &op, bool real, C *v, const R *pool,
+                                            const PassTermDev *terms, uint32_t t, uint64_t base, bool tok) {
+    const R *m = pool + op.mat;
+#define QSV_G1(I)                                                               \
+    case I:                                                                     \
+        if constexpr (I < RB) {                                                 \
+            if (op.pre) pre_phase<C, R, NR, RB, I>(v, op, terms, pool, t, base); \
+            if (real) g1r<C, R, NR, I>(v, m, op.cj, tok);                       \
+            else g1<C, R, NR, I>(v, m, op.cj, tok);                             \
+        }                                                                       \
         break;
-    switch (a) {
+    switch (op.a) {
         QSV_G1(0) QSV_G1(1) QSV_G1(2) QSV_G1(3) QSV_G1(4)
     }
 #undef QSV_G1
@@ -151,9 +158,25 @@ __device__ __forceinline__ double2 rot(double2 v, uint64_t ph) {
     return r;
 }
 
-template <typename C, int NR, int RB>
-__device__ __forceinline__ void phase_op(C *v, const PassOpDev &op, const PassTermDev *terms, uint32_t t,
-                                         uint64_t base) {
+__device__ __forceinline__ float2 expi(uint64_t ph, float) {
+    const float x = (float)(int32_t)(uint32_t)(ph >> 32) * 2.3283064365386963e-10f;
+    float2 r;
+    sincospif(2.0f * x, &r.y, &r.x);
+    return r;
+}
+__device__ __forceinline__ double2 expi(uint64_t ph, double) {
+    const double x = (double)(int64_t)ph * 5.421010862427522e-20;
+    double2 r;
+    sincospi(2.0 * x, &r.y, &r.x);
+    return r;
+}
+
+// Factor table f[j] of a grouped phase (see PassOpDev) for every register
+// index j with bit SKIP clear (SKIP = -1: every j).  Terms of the last group
+// are not included (evaluated per j by the caller).
+template <typename C, typename R, int NR, int RB, int SKIP>
+__device__ __forceinline__ void phase_table(C *f, const PassOpDev &op, const PassTermDev *terms, const R *pool,
+                                            uint32_t t, uint64_t base) {
     constexpr int NQ = RB * (RB - 1) / 2;
     auto sum_group = [&](int g) -> uint64_t {
         uint64_t s = 0;
@@ -165,31 +188,86 @@ __device__ __forceinline__ void phase_op(C *v, const PassOpDev &op, const PassTe
         }
         return s;
     };
-    const uint64_t c0 = sum_group(0);
-    uint64_t lin[RB];
+    C one;
+    one.x = 1;
+    one.y = 0;
+    f[0] = (op.grp[1] > op.grp[0]) ? expi(sum_group(0), R()) : one;
+    C E[RB];
 #pragma unroll
-    for (int i = 0; i < RB; ++i) lin[i] = sum_group(1 + i);
-    uint64_t quad[NQ > 0 ? NQ : 1];
+    for (int i = 0; i < RB; ++i) E[i] = (i != SKIP && op.grp[2 + i] > op.grp[1 + i]) ? expi(sum_group(1 + i), R()) : one;
+    C Q[NQ > 0 ? NQ : 1];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) quad[q] = sum_group(1 + RB + q);
+    for (int q = 0; q < NQ; ++q) {
+        Q[q].x = pool[op.qf + 2 * q];
+        Q[q].y = pool[op.qf + 2 * q + 1];
+    }
+    // f[rest | 2^top] = f[rest] * E[top] * prod_{i in rest} Q[top, i]
+#pragma unroll
+    for (int top = 0; top < RB; ++top) {
+        if (top == SKIP) continue;
+        C Rt[1 << (RB - 1)];
+#pragma unroll
+        for (int rest = 0; rest < (1 << top); ++rest) {
+            if (SKIP >= 0 && ((rest >> SKIP) & 1)) continue;
+            if (rest == 0) {
+                Rt[0] = E[top];
+            } else {
+                const int hb = 31 - __builtin_clz(rest);
+                Rt[rest] = cmul(Rt[rest ^ (1 << hb)], Q[top * (top - 1) / 2 + hb]);
+            }
+            f[rest | (1 << top)] = cmul(f[rest], Rt[rest]);
+        }
+    }
+}
+
+template <typename C, typename R, int NR, int RB>
+__device__ __forceinline__ void phase_op(C *v, const PassOpDev &op, const PassTermDev *terms, const R *pool,
+                                         uint32_t t, uint64_t base) {
+    constexpr int NQ = RB * (RB - 1) / 2;
+    C f[NR];
+    phase_table<C, R, NR, RB, -1>(f, op, terms, pool, t, base);
     const int gen_b = op.grp[1 + RB + NQ], gen_e = op.grp[2 + RB + NQ];
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
-        uint64_t ph = c0;
-#pragma unroll
-        for (int i = 0; i < RB; ++i)
-            if ((j >> i) & 1) ph += lin[i];
-#pragma unroll
-        for (int i1 = 1; i1 < RB; ++i1)
-#pragma unroll
-            for (int i2 = 0; i2 < i1; ++i2)
-                if (((j >> i1) & 1) && ((j >> i2) & 1)) ph += quad[i1 * (i1 - 1) / 2 + i2];
-        for (int k = gen_b; k < gen_e; ++k) {
-            const PassTermDev tm = terms[k];
-            const bool ok = ((t & tm.mt) == tm.mt) && ((base & tm.mn) == tm.mn) && (((uint32_t)j & tm.mj) == tm.mj);
-            ph += ok ? tm.theta : 0ull;
+        C x = cmul(v[j], f[j]);
+        if (gen_e > gen_b) {
+            uint64_t ph = 0;
+            for (int k = gen_b; k < gen_e; ++k) {
+                const PassTermDev tm = terms[k];
+                const bool ok =
+                    ((t & tm.mt) == tm.mt) && ((base & tm.mn) == tm.mn) && (((uint32_t)j & tm.mj) == tm.mj);
+                ph += ok ? tm.theta : 0ull;
+            }
+            x = rot(x, ph);
         }
-        v[j] = rot(v[j], ph);
+        v[j] = x;
+    }
+}
+
+// The phase that precedes a one-qubit gate on register bit I multiplies only
+// its |1> members: apply it to v[j | 2^I] for every j with bit I clear.
+template <typename C, typename R, int NR, int RB, int I>
+__device__ __forceinline__ void pre_phase(C *v, const PassOpDev &op, const PassTermDev *terms, const R *pool,
+                                          uint32_t t, uint64_t base) {
+    constexpr int NQ = RB * (RB - 1) / 2;
+    C f[NR];
+    phase_table<C, R, NR, RB, I>(f, op, terms, pool, t, base);
+    const int gen_b = op.grp[1 + RB + NQ], gen_e = op.grp[2 + RB + NQ];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        if ((j >> I) & 1) continue;
+        C x = cmul(v[j | (1 << I)], f[j]);
+        if (gen_e > gen_b) {
+            uint64_t ph = 0;
+            for (int k = gen_b; k < gen_e; ++k) {
+                const PassTermDev tm = terms[k];
+                const bool ok =
+                    ((t & tm.mt) == tm.mt) && ((base & tm.mn) == tm.mn) && (((uint32_t)j & tm.mj) == tm.mj);
+                ph += ok ? tm.theta : 0ull;
+            }
+            x = rot(x, ph);
+        }
+        v[j | (1 << I)] = x;
     }
 }
 
@@ -240,10 +318,10 @@ __global__ void __launch_bounds__(PT) k_pass(typename cplx_of<R>::type *__restri
             const PassOpDev &op = ops[o];
             const bool tok = ((t & op.ct) == op.ct) && ((base & op.cn) == op.cn);
             switch (op.kind) {
-            case POP_G1: dispatch_g1<C, R, NR, RB>(op.a, false, v, pool + op.mat, op.cj, tok); break;
-            case POP_G1R: dispatch_g1<C, R, NR, RB>(op.a, true, v, pool + op.mat, op.cj, tok); break;
+            case POP_G1: dispatch_g1<C, R, NR, RB>(op, false, v, pool, terms, t, base, tok); break;
+            case POP_G1R: dispatch_g1<C, R, NR, RB>(op, true, v, pool, terms, t, base, tok); break;
             case POP_G2: dispatch_g2<C, R, NR, RB>(op.a, op.b, v, pool + op.mat, op.cj, tok); break;
-            case POP_PHASE: phase_op<C, NR, RB>(v, op, terms, t, base); break;
+            case POP_PHASE: phase_op<C, R, NR, RB>(v, op, terms, pool, t, base); break;
             case POP_EXCHANGE: {
                 const PassPartition &P = parts[cur];
                 const PassPartition &Q = parts[op.a];
@@ -280,6 +358,10 @@ __global__ void __launch_bounds__(PT) k_pass(typename cplx_of<R>::type *__restri
             }
         }
         {
+            // A thread may store to addresses another thread of the chunk
+            // loaded (relabelled local bits, or a partition change without
+            // an exchange in between): every load of the chunk must be done.
+            if (H->relabel) __syncthreads();
             const PassPartition &P = parts[cur];
             uint64_t gt = base;
 #pragma unroll
@@ -311,7 +393,12 @@ void PassProgram::serialise() {
         h.in_pos[l] = local_sorted[l];
         h.out_pos[l] = out_pos[l];
         h.lowmask[l] = (1ull << local_sorted[l]) - 1ull;
+        if (out_pos[l] != local_sorted[l]) h.relabel = 1;
     }
+    // An exchange's barriers already order every load before any store; only
+    // relabelled positions in a pass without exchanges need the extra barrier.
+    for (const auto &op : ops)
+        if (op.kind == POP_EXCHANGE) h.relabel = 0;
     auto align = [](size_t x) { return (x + 15) & ~(size_t)15; };
     size_t off = align(sizeof(PassHeaderDev));
     h.off_part = (int)off;

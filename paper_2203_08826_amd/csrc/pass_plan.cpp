@@ -96,6 +96,9 @@ struct LOp {                        // an op in local-position space
     uint64_t gc = 0;                // non-local control bits
     std::vector<double> M;
     std::vector<std::pair<uint64_t, std::pair<uint32_t, uint64_t>>> terms;   // PHASE: (theta, (lmask, gmask))
+    // one-target NONDIAG: phase terms (all containing the target) applied to
+    // the |1> member just before the gate
+    std::vector<std::pair<uint64_t, std::pair<uint32_t, uint64_t>>> pre;
 };
 
 struct Part {
@@ -151,7 +154,7 @@ int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> 
     std::vector<LOp> ops;
     LOp pending;
     pending.phase = true;
-    auto flush = [&](uint32_t blocking, bool all) {
+    auto flush = [&](uint32_t blocking, bool all, LOp *attach) {
         LOp out;
         out.phase = true;
         std::vector<std::pair<uint64_t, std::pair<uint32_t, uint64_t>>> keep;
@@ -160,7 +163,9 @@ int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> 
             else keep.push_back(t);
         }
         pending.terms.swap(keep);
-        if (!out.terms.empty()) ops.push_back(std::move(out));
+        if (out.terms.empty()) return;
+        if (attach) attach->pre.swap(out.terms);
+        else ops.push_back(std::move(out));
     };
     for (const PGate &g : gates) {
         switch (g.kind) {
@@ -195,14 +200,14 @@ int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> 
                 else op.gc |= 1ull << q;
             }
             op.M = g.M;
-            flush(tmask, false);
+            flush(tmask, false, op.lt.size() == 1 ? &op : nullptr);
             ops.push_back(std::move(op));
             break;
         }
         default: return fail(QSV_ERR_ARG, "internal: gate kind not allowed in a pass");
         }
     }
-    flush(0, true);
+    flush(0, true, nullptr);
 
     // store map: local position l holds logical qubit q with cur_l[q] == l
     prog.out_pos.assign(L, -1);
@@ -257,6 +262,55 @@ int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> 
         prog.ops.push_back(d);
         cur = np;
     };
+    // Group phase terms by the register bits they need under `cur` (see
+    // PassOpDev); `skip` is a local position removed from every term (the
+    // target of a pre-phased G1, implied by its |1> member).
+    const int NQ = RB * (RB - 1) / 2;
+    const int ngroups = 1 + RB + NQ + 1;
+    auto encode_terms = [&](const std::vector<std::pair<uint64_t, std::pair<uint32_t, uint64_t>>> &terms, int skip,
+                            PassOpDev &d) {
+        std::vector<std::vector<PassTermDev>> groups(ngroups);
+        std::vector<uint64_t> qconst(NQ > 0 ? NQ : 1, 0);
+        for (auto &t : terms) {
+            PassTermDev td;
+            std::memset(&td, 0, sizeof(td));
+            td.theta = t.first;
+            td.mn = t.second.second;
+            std::vector<int> regs;
+            for (int l = 0; l < L; ++l) {
+                if (!((t.second.first >> l) & 1) || l == skip) continue;
+                const int i = reg_index(cur, l);
+                if (i >= 0) {
+                    regs.push_back(i);
+                    td.mj |= 1u << i;
+                } else {
+                    td.mt |= 1u << thr_index(cur, l);
+                }
+            }
+            int gidx;
+            if (regs.empty()) gidx = 0;
+            else if (regs.size() == 1) gidx = 1 + regs[0];
+            else if (regs.size() == 2 && td.mt == 0 && td.mn == 0) {
+                const int a = std::max(regs[0], regs[1]), b = std::min(regs[0], regs[1]);
+                qconst[a * (a - 1) / 2 + b] += td.theta;   // constant: folded into a host factor
+                continue;
+            } else gidx = ngroups - 1;
+            groups[gidx].push_back(td);
+        }
+        int k = (int)prog.terms.size();
+        for (int g = 0; g < ngroups; ++g) {
+            d.grp[g] = k;
+            for (auto &td : groups[g]) prog.terms.push_back(td);
+            k = (int)prog.terms.size();
+        }
+        d.grp[ngroups] = k;
+        d.qf = (int)prog.pool.size();
+        for (int q = 0; q < NQ; ++q) {
+            const double ang = 2.0 * M_PI * ((double)(int64_t)qconst[q] * 5.421010862427522e-20);
+            prog.pool.push_back(std::cos(ang));
+            prog.pool.push_back(std::sin(ang));
+        }
+    };
     for (size_t o = 0; o < ops.size(); ++o) {
         const LOp &op = ops[o];
         PassOpDev d;
@@ -280,6 +334,11 @@ int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> 
             d.mat = (int)prog.pool.size();
             if (op.lt.size() == 1) {
                 d.a = reg_index(cur, op.lt[0]);
+                if (!op.pre.empty()) {
+                    d.pre = 1;
+                    encode_terms(op.pre, op.lt[0], d);
+                }
+                d.mat = (int)prog.pool.size();
                 bool real = true;
                 for (int e = 0; e < 4; ++e)
                     if (op.M[2 * e + 1] != 0.0) real = false;
@@ -310,42 +369,7 @@ int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> 
             }
         } else {
             d.kind = POP_PHASE;
-            // group the terms by the register bits they need under `cur`
-            const int NQ = RB * (RB - 1) / 2;
-            const int ngroups = 1 + RB + NQ + 1;
-            std::vector<std::vector<PassTermDev>> groups(ngroups);
-            for (auto &t : op.terms) {
-                PassTermDev td;
-                std::memset(&td, 0, sizeof(td));
-                td.theta = t.first;
-                td.mn = t.second.second;
-                std::vector<int> regs;
-                for (int l = 0; l < L; ++l) {
-                    if (!((t.second.first >> l) & 1)) continue;
-                    const int i = reg_index(cur, l);
-                    if (i >= 0) {
-                        regs.push_back(i);
-                        td.mj |= 1u << i;
-                    } else {
-                        td.mt |= 1u << thr_index(cur, l);
-                    }
-                }
-                int gidx;
-                if (regs.empty()) gidx = 0;
-                else if (regs.size() == 1) gidx = 1 + regs[0];
-                else if (regs.size() == 2) {
-                    const int a = std::max(regs[0], regs[1]), b = std::min(regs[0], regs[1]);
-                    gidx = 1 + RB + a * (a - 1) / 2 + b;
-                } else gidx = ngroups - 1;
-                groups[gidx].push_back(td);
-            }
-            int k = (int)prog.terms.size();
-            for (int g = 0; g < ngroups; ++g) {
-                d.grp[g] = k;
-                for (auto &td : groups[g]) prog.terms.push_back(td);
-                k = (int)prog.terms.size();
-            }
-            d.grp[ngroups] = k;
+            encode_terms(op.terms, -1, d);
         }
         prog.ops.push_back(d);
     }
@@ -397,11 +421,28 @@ int build_passes(qsv_plan *p, int local_bits) {
     }
     const int L = RB + PASS_THREAD_BITS;
     const int lanes = std::min(LANE_BITS, L - RB);
-    std::vector<PGate> pgs(p->gates.size());
-    for (size_t i = 0; i < p->gates.size(); ++i) {
-        int st = classify(p->gates[i], pgs[i]);
+    // SWAP gates become relabellings: logical qubit q lives at physical bit
+    // phys[q]; every other gate is rewritten onto physical bits.
+    std::vector<int> phys(n);
+    for (int q = 0; q < n; ++q) phys[q] = q;
+    std::vector<qsv_gate> gates;
+    for (const auto &g0 : p->gates) {
+        if (g0.kind == QSV_GATE_SWAP && g0.c == 0) {
+            std::swap(phys[g0.targets[0]], phys[g0.targets[1]]);
+            continue;
+        }
+        qsv_gate g = g0;
+        for (int j = 0; j < g.k; ++j) g.targets[j] = phys[g0.targets[j]];
+        for (int j = 0; j < g.c; ++j) g.controls[j] = phys[g0.controls[j]];
+        gates.push_back(g);
+    }
+    std::vector<PGate> pgs(gates.size());
+    for (size_t i = 0; i < gates.size(); ++i) {
+        int st = classify(gates[i], pgs[i]);
         if (st) return st;
         pgs[i].gi = (int)i;
+        // a two-qubit gate needs two register bits
+        if (pgs[i].kind == PGate::NONDIAG && pgs[i].targets.size() > (size_t)RB) pgs[i].kind = PGate::OTHER;
     }
     std::vector<PGate> run;
     uint64_t S = 0;   // local set (global bits) of the open pass
@@ -439,7 +480,7 @@ int build_passes(qsv_plan *p, int local_bits) {
         PGate &g = pgs[i];
         if (g.kind == PGate::OTHER) {
             int st = close();
-            if (!st) st = plan_add_gate_op(p, p->gates[i]);
+            if (!st) st = plan_add_gate_op(p, gates[i]);
             if (st) return st;
             continue;
         }
@@ -453,7 +494,48 @@ int build_passes(qsv_plan *p, int local_bits) {
         S |= need;
         run.push_back(g);
     }
-    return close();
+    int st = close();
+    if (st) return st;
+    // undo the relabelling: data of logical qubit q sits at bit phys[q]
+    std::vector<int> sigma(n);
+    bool moved = false;
+    for (int q = 0; q < n; ++q) {
+        sigma[phys[q]] = q;
+        if (phys[q] != q) moved = true;
+    }
+    if (!moved) return QSV_OK;
+    bool involution = true;
+    for (int b = 0; b < n; ++b)
+        if (sigma[sigma[b]] != b) involution = false;
+    const double s_amp = p->dtype == QSV_C64 ? 8.0 : 16.0;
+    if (involution) {
+        PlanOp op;
+        op.kind = PlanOp::PERM;
+        op.sigma = sigma;
+        op.bytes = 2.0 * std::ldexp(1.0, n) * s_amp;
+        p->ops.push_back(std::move(op));
+        p->stats.n_passes++;
+        return QSV_OK;
+    }
+    // otherwise physical SWAPs, one per misplaced qubit
+    std::vector<int> at(n);   // at[b] = logical qubit held by physical bit b
+    for (int q = 0; q < n; ++q) at[phys[q]] = q;
+    for (int b = 0; b < n; ++b) {
+        if (at[b] == b) continue;
+        const int other = phys[b];   // physical bit holding logical qubit b
+        qsv_gate g;
+        std::memset(&g, 0, sizeof(g));
+        g.kind = QSV_GATE_SWAP;
+        g.k = 2;
+        g.targets[0] = b;
+        g.targets[1] = other;
+        if ((st = plan_add_gate_op(p, g))) return st;
+        const int qb = at[b];
+        std::swap(at[b], at[other]);
+        phys[qb] = other;
+        phys[b] = b;
+    }
+    return QSV_OK;
 }
 
 int build_single_pass(int n, int dtype, const std::vector<qsv_gate> &gates, const std::vector<int> &local,
@@ -473,7 +555,7 @@ int build_single_pass(int n, int dtype, const std::vector<qsv_gate> &gates, cons
     for (size_t i = 0; i < gates.size(); ++i) {
         int st = classify(gates[i], pgs[i]);
         if (st) return st;
-        if (pgs[i].kind == PGate::OTHER)
+        if (pgs[i].kind == PGate::OTHER || (pgs[i].kind == PGate::NONDIAG && pgs[i].targets.size() > (size_t)RB))
             return fail(QSV_ERR_UNSUPPORTED, "gate " + std::to_string(i) + " cannot run in a pass (dense k > 2 or non-unitary diagonal)");
         if (pgs[i].kind != PGate::PHASE)
             for (int q : pgs[i].targets)

@@ -3,15 +3,10 @@
 #include "plan_internal.h"
 using namespace qsv;
 namespace qsv {
-int launch_block_mfma(void *state, int n, const double *G, const int *targets, int k, hipStream_t s) {
-    GateAnalysis a = analyse_gate(n, G, targets, k, nullptr, 0);
-    return launch_gate(state, QSV_C64, a, s);
-}
 int build_learned(qsv_plan *p) { return build_greedy(p, p->opts.kmax, p->opts.use_mfma != 0); }
 }
 extern "C" {
 static int nyi(const char *f) { return fail(QSV_ERR_UNSUPPORTED, std::string(f) + ": not in this build"); }
-int qsv_apply_block(void *, int, int, const void *, const int *, int, void *) { return nyi("qsv_apply_block"); }
 int qsv_adjoint_grad(void *, void *, int, int, const qsv_gate *, int, double *, void *) { return nyi("qsv_adjoint_grad"); }
 int qsv_mlp_forward(const float *, const int *, int, const float *, int, float *, float *, void *) { return nyi("qsv_mlp_forward"); }
 int qsv_mlp_backward(const float *, const int *, int, const float *, int, const float *, const float *, const float *, float *, float *, void *) { return nyi("qsv_mlp_backward"); }

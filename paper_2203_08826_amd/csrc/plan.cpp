@@ -144,7 +144,7 @@ int plan_add_gate_op(qsv_plan *p, const qsv_gate &g) {
 int plan_add_block_op(qsv_plan *p, const std::vector<int> &qubits, const std::vector<double> &M, bool allow_mfma) {
     const int kb = (int)qubits.size();
     PlanOp op;
-    const bool mfma = allow_mfma && p->dtype == QSV_C64 && kb >= 4 && kb <= 6 && p->n >= kb + 1;
+    const bool mfma = allow_mfma && p->dtype == QSV_C64 && kb >= 4 && kb <= 6 && p->n >= kb + 5;
     op.analysis = analyse_gate(p->n, M.data(), qubits.data(), kb, nullptr, 0);
     if (mfma && op.analysis.cls == GC_DENSE && (int)op.analysis.members.size() == (1 << kb)) {
         op.kind = PlanOp::MFMA_BLOCK;
@@ -201,6 +201,7 @@ int execute_op(const qsv_plan *p, const PlanOp &op, void *state, hipStream_t s) 
     case PlanOp::MFMA_BLOCK:
         return launch_block_mfma(state, p->n, op.matrix.data(), op.qubits.data(), (int)op.qubits.size(), s);
     case PlanOp::PASS: return launch_pass_program(state, p->n, p->dtype, *op.pass, s);
+    case PlanOp::PERM: return launch_bitperm(state, p->n, p->dtype, op.sigma, s);
     }
     return fail(QSV_ERR_ARG, "internal: unknown op kind");
 }
@@ -304,6 +305,22 @@ int qsv_plan_op_info(const qsv_plan *plan, int index, int *kind, double *bytes, 
     if (kind) *kind = (int)op.kind;
     if (bytes) *bytes = op.bytes;
     if (flops) *flops = op.flops;
+    return QSV_OK;
+}
+
+int qsv_plan_op_program(const qsv_plan *plan, int index, void *buf, size_t cap, size_t *size) {
+    if (!plan || !size) return fail(QSV_ERR_NULL, "NULL argument");
+    if (index < 0 || index >= (int)plan->ops.size()) return fail(QSV_ERR_ARG, "op index out of bounds");
+    const PlanOp &op = plan->ops[index];
+    if (op.kind != PlanOp::PASS) return fail(QSV_ERR_ARG, "op is not an LDS pass");
+    std::vector<uint8_t> blob = op.pass->blob;
+    const PassHeaderDev *h = (const PassHeaderDev *)blob.data();
+    std::memcpy(blob.data() + h->off_pool, op.pass->pool.data(), op.pass->pool.size() * sizeof(double));
+    *size = blob.size();
+    if (buf) {
+        if (cap < blob.size()) return fail(QSV_ERR_ARG, "buffer too small");
+        std::memcpy(buf, blob.data(), blob.size());
+    }
     return QSV_OK;
 }
 

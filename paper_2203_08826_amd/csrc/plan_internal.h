@@ -31,6 +31,15 @@ struct PassPartition {
     int32_t thr_l[PASS_THREAD_BITS];     // local position of thread bit u
 };
 
+// Phase evaluation (PHASE ops, and the phase a G1/G1R op applies to its
+// |1> member first when `pre` is set): terms are grouped by the register
+// bits they need under the op's partition --
+//   group 0        : no register bit      -> per-thread sum A0
+//   group 1 + i    : register bit i only  -> per-thread sum A_i
+//   group 1+RB+q   : register pair q      -> constant, host factor in the pool at qf
+//   last group     : everything else      -> evaluated per register index
+// and the factor of register index j is e^{iA0} prod_{i in j} e^{iA_i}
+// prod_{pairs in j} Q_pair, built as a product table.
 struct PassOpDev {
     int32_t kind;
     int32_t a, b;          // G1: register bit a.  G2: register bits a > b.  EXCHANGE: partition index
@@ -38,7 +47,9 @@ struct PassOpDev {
     uint32_t cj;           // controls on register bits (mask over j)
     int32_t mat;           // offset into the real pool
     uint64_t cn;           // controls on non-local bits (mask over global index)
-    int32_t grp[PASS_GROUPS + 1];   // PHASE: term ranges [grp[g], grp[g+1]) per group
+    int32_t grp[PASS_GROUPS + 1];   // term ranges [grp[g], grp[g+1]) per group
+    int32_t qf;            // pool offset of the constant pair factors (complex, one per pair)
+    int32_t pre;           // G1/G1R: apply the grouped phase to the |1> member first
 };
 
 // Phase term: contributes theta (fixed-point turns, 2^64 = one turn) when
@@ -61,7 +72,7 @@ struct PassHeaderDev {
     uint64_t lowmask[PASS_MAX_L];  // sorted local bits, for the chunk base
     int32_t off_part, off_ops, off_pool, off_terms;   // byte offsets from the header
     int32_t total_bytes;
-    int32_t pad;
+    int32_t relabel;               // 1: some thread stores where another loaded
 };
 
 // Host-side pass program (what the planner emits, before serialisation).
@@ -81,11 +92,13 @@ struct PassProgram {
 };
 
 int launch_pass_program(void *state, int n, int dtype, const PassProgram &prog, hipStream_t s);
+int launch_bitperm(void *state, int n, int dtype, const std::vector<int> &sigma, hipStream_t s);
 
 // ---------------------------------------------------------------- plans
 
 struct PlanOp {
-    enum Kind { GATE = 0, MFMA_BLOCK = 1, PASS = 2 } kind = GATE;
+    enum Kind { GATE = 0, MFMA_BLOCK = 1, PASS = 2, PERM = 3 } kind = GATE;
+    std::vector<int> sigma;                // PERM: destination bit of every source bit (an involution)
     GateAnalysis analysis;                 // GATE
     std::vector<int> qubits;               // MFMA_BLOCK: block qubits (targets[0] = MSB)
     std::vector<double> matrix;            // MFMA_BLOCK: complex128 4^k

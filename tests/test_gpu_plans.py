@@ -56,6 +56,47 @@ def test_greedy_widths(gpu, kmax):
         assert np.max(np.abs(got - want)) <= TOL[dt], (kmax, dt)
 
 
+@pytest.mark.parametrize("dt", [qsv.QSV_C64, qsv.QSV_C128])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_swap_networks_in_passes(gpu, dt, seed):
+    """SWAPs become relabellings in pass plans; the leftover permutation is
+    moved by the bit-permutation kernel (involutions) or by SWAP kernels."""
+    import torch
+    n = 17
+    rng = np.random.default_rng(seed)
+    circ = []
+    for _ in range(25):
+        a, b = [int(x) for x in rng.choice(n, 2, replace=False)]
+        circ.append(W.gate("SWAP", [a, b]))
+        if rng.integers(3) == 0:
+            circ.append(W.gate("H", [int(rng.integers(n))]))
+    if seed == 0:
+        circ = [W.gate("SWAP", [i, n - 1 - i]) for i in range(n // 2)] + [W.gate("H", [3])]
+    psi0 = W.random_state(n, seed)
+    want = S.run_circuit(psi0, circ)
+    got, stats = _run(psi0, circ, dt, mode=qsv.PLAN_PASSES)
+    assert np.max(np.abs(got - want)) <= TOL[dt], stats
+    # a pure permutation moves amplitudes bit-exactly
+    perm_only = [g for g in circ if g["name"] == "SWAP"]
+    t = torch.complex64 if dt == qsv.QSV_C64 else torch.complex128
+    st = torch.from_numpy(psi0).to(t).cuda()
+    ref = st.clone()
+    plan = qsv.qsv_plan_create(n, dt, perm_only, mode=qsv.PLAN_PASSES)
+    qsv.qsv_plan_execute(plan, st)
+    idx = np.arange(1 << n)
+    src = idx.copy()
+    for g in perm_only:
+        a, b = g["targets"]
+        ba, bb = (src >> a) & 1, (src >> b) & 1
+    # out[i] = in[perm(i)]: apply each swap to the index
+    out_idx = idx.copy()
+    for g in reversed(perm_only):
+        a, b = g["targets"]
+        ba, bb = (out_idx >> a) & 1, (out_idx >> b) & 1
+        out_idx = out_idx & ~((1 << a) | (1 << b)) | (bb << a) | (ba << b)
+    assert torch.equal(st.cpu(), ref.cpu()[torch.from_numpy(out_idx)])
+
+
 def test_qft20_passes_c128_against_fft(gpu):
     n = 20
     psi0 = W.random_state(n, 0)
