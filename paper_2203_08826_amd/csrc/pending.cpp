@@ -7,7 +7,6 @@ int build_learned(qsv_plan *p) { return build_greedy(p, p->opts.kmax, p->opts.us
 }
 extern "C" {
 static int nyi(const char *f) { return fail(QSV_ERR_UNSUPPORTED, std::string(f) + ": not in this build"); }
-int qsv_adjoint_grad(void *, void *, int, int, const qsv_gate *, int, double *, void *) { return nyi("qsv_adjoint_grad"); }
 int qsv_mlp_forward(const float *, const int *, int, const float *, int, float *, float *, void *) { return nyi("qsv_mlp_forward"); }
 int qsv_mlp_backward(const float *, const int *, int, const float *, int, const float *, const float *, const float *, float *, float *, void *) { return nyi("qsv_mlp_backward"); }
 int qsv_mlp_adam(float *, const float *, float *, float *, int, int, float, float, float, float, void *) { return nyi("qsv_mlp_adam"); }
