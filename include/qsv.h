@@ -268,16 +268,19 @@ int qsv_mlp_adam(float *params, const float *grads, float *m, float *v, int coun
 int qsv_mlp_param_count(const int *sizes, int nlayers);
 
 /* Cost model used by QSV_PLAN_LEARNED: a copy of the parameters (host FP32,
- * layout as above) and the feature normalisation (mean, scale per input).
- * Passing nlayers = 0 removes the model. */
+ * layout as above, sizes[0] == QSV_COST_FEATURES) and the feature
+ * normalisation (x - mean) / scale per input.  The network predicts the
+ * natural log of an op's run time in seconds.  Passing nlayers = 0 removes
+ * the model.  The model is process-wide; the call copies everything. */
 int qsv_cost_model_set(const float *params, const int *sizes, int nlayers,
                        const float *feat_mean, const float *feat_scale);
-/* Host-only: the feature vector (QSV_COST_FEATURES floats) of one candidate
- * op, for training data.  variant: 0 = per-gate, 1 = dense block (VALU),
- * 2 = MFMA block, 3 = LDS pass. */
+/* Host-only: the raw feature vector (QSV_COST_FEATURES floats) of op `index`
+ * of a plan -- n, dtype, one-hot variant (single-gate kernel, fused block on
+ * the VALU kernels, MFMA block, LDS pass, bit permutation), number of
+ * qubits, number of qubits below 5, log2 bytes, log2 flops, and an
+ * op-specific size (log2 touched members, or ops in a pass program). */
 #define QSV_COST_FEATURES 12
-int qsv_cost_features(int n, int dtype, int variant, const int *qubits, int nq, int n_members,
-                      int is_diag, int is_perm, float *out);
+int qsv_plan_op_features(const qsv_plan *plan, int index, float *out);
 
 #ifdef __cplusplus
 }

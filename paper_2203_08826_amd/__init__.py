@@ -408,9 +408,8 @@ def qsv_cost_model_clear():
     check("qsv_cost_model_set", load().qsv_cost_model_set(None, s, 0, None, None))
 
 
-def qsv_cost_features(n, dtype, variant, qubits, n_members, is_diag=False, is_perm=False):
-    q, nq = _ints(qubits)
+def qsv_plan_op_features(plan, index):
+    """Host-only: raw cost-model features of op `index` of a plan."""
     out = np.empty(COST_FEATURES, dtype=np.float32)
-    check("qsv_cost_features", load().qsv_cost_features(int(n), int(dtype), int(variant), q, nq, int(n_members),
-                                                        int(bool(is_diag)), int(bool(is_perm)), out.ctypes.data))
+    check("qsv_plan_op_features", load().qsv_plan_op_features(plan._h, int(index), out.ctypes.data))
     return out

@@ -156,6 +156,7 @@ int plan_add_block_op(qsv_plan *p, const std::vector<int> &qubits, const std::ve
         p->stats.n_mfma_blocks++;
     } else {
         op.kind = PlanOp::GATE;
+        op.fused = true;
         op.bytes = op_bytes(op.analysis, p->dtype);
         op.flops = op_flops(op.analysis);
     }

@@ -103,6 +103,7 @@ struct PlanOp {
     std::vector<int> qubits;               // MFMA_BLOCK: block qubits (targets[0] = MSB)
     std::vector<double> matrix;            // MFMA_BLOCK: complex128 4^k
     std::shared_ptr<PassProgram> pass;     // PASS
+    bool fused = false;                    // GATE built from a fused block of several gates
     double bytes = 0, flops = 0;
 };
 
