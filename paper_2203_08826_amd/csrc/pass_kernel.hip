@@ -179,14 +179,21 @@ __device__ __forceinline__ void phase_table(C *f, const PassOpDev &op, const Pas
                                             uint32_t t, uint64_t base) {
     constexpr int NQ = RB * (RB - 1) / 2;
     auto sum_group = [&](int g) -> uint64_t {
+        // chunk-only terms first: every operand is wave-uniform (scalar unit)
+        uint64_t su = 0;
+        const int u = op.grpu[g];
+        for (int k = op.grp[g]; k < u; ++k) {
+            const PassTermDev tm = terms[k];
+            su += ((base & tm.mn) == tm.mn) ? tm.theta : 0ull;
+        }
         uint64_t s = 0;
         const int e = op.grp[g + 1];
-        for (int k = op.grp[g]; k < e; ++k) {
+        for (int k = u; k < e; ++k) {
             const PassTermDev tm = terms[k];
             const bool ok = ((t & tm.mt) == tm.mt) && ((base & tm.mn) == tm.mn);
             s += ok ? tm.theta : 0ull;
         }
-        return s;
+        return su + s;
     };
     C one;
     one.x = 1;

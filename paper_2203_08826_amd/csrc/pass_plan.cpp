@@ -300,7 +300,12 @@ int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> 
         int k = (int)prog.terms.size();
         for (int g = 0; g < ngroups; ++g) {
             d.grp[g] = k;
-            for (auto &td : groups[g]) prog.terms.push_back(td);
+            // chunk-only terms (no thread bit) first, so the device sums them on the scalar unit
+            for (auto &td : groups[g])
+                if (td.mt == 0) prog.terms.push_back(td);
+            d.grpu[g] = (int)prog.terms.size();
+            for (auto &td : groups[g])
+                if (td.mt != 0) prog.terms.push_back(td);
             k = (int)prog.terms.size();
         }
         d.grp[ngroups] = k;
