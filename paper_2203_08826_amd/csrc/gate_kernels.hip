@@ -59,55 +59,102 @@ __device__ inline uint64_t group_base(uint64_t g, const GroupArgs &ga) {
     return i | ga.cmask;
 }
 
+// Groups per thread per loop iteration: several independent groups keep
+// enough loads in flight to cover HBM latency when a group is small.
+template <int M> struct Unroll { static constexpr int U = M <= 2 ? 4 : (M <= 4 ? 2 : 1); };
+
 template <typename C, int M>
 __global__ void __launch_bounds__(256) k_dense(C *__restrict__ psi, GroupArgs ga, DenseArgs<C, M> da) {
+    constexpr int U = Unroll<M>::U;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ga.ngroups; g += stride) {
-        const uint64_t base = group_base(g, ga);
-        C v[M];
+    for (uint64_t g0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < ga.ngroups; g0 += U * stride) {
+        uint64_t base[U];
+        bool live[U];
+        C v[U][M];
 #pragma unroll
-        for (int j = 0; j < M; ++j) v[j] = psi[base + da.offs[j]];
+        for (int u = 0; u < U; ++u) {
+            const uint64_t g = g0 + u * stride;
+            live[u] = g < ga.ngroups;
+            base[u] = live[u] ? group_base(g, ga) : 0;
+        }
 #pragma unroll
-        for (int r = 0; r < M; ++r) {
-            C acc;
-            acc.x = 0;
-            acc.y = 0;
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int j = 0; j < M; ++j) {
-                const C gm = (M <= 8) ? da.mat[r * M + j] : da.dmat[r * M + j];
-                acc = cfma(gm, v[j], acc);
+            for (int j = 0; j < M; ++j)
+                if (live[u]) v[u][j] = psi[base[u] + da.offs[j]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!live[u]) continue;
+#pragma unroll
+            for (int r = 0; r < M; ++r) {
+                C acc;
+                acc.x = 0;
+                acc.y = 0;
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    const C gm = (M <= 8) ? da.mat[r * M + j] : da.dmat[r * M + j];
+                    acc = cfma(gm, v[u][j], acc);
+                }
+                psi[base[u] + da.offs[r]] = acc;
             }
-            psi[base + da.offs[r]] = acc;
         }
     }
 }
 
 template <typename C, int M>
 __global__ void __launch_bounds__(256) k_diag(C *__restrict__ psi, GroupArgs ga, DiagArgs<C, M> da) {
+    constexpr int U = Unroll<M>::U;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ga.ngroups; g += stride) {
-        const uint64_t base = group_base(g, ga);
-        C v[M];
+    for (uint64_t g0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < ga.ngroups; g0 += U * stride) {
+        uint64_t base[U];
+        bool live[U];
+        C v[U][M];
 #pragma unroll
-        for (int j = 0; j < M; ++j) v[j] = psi[base + da.offs[j]];
+        for (int u = 0; u < U; ++u) {
+            const uint64_t g = g0 + u * stride;
+            live[u] = g < ga.ngroups;
+            base[u] = live[u] ? group_base(g, ga) : 0;
+        }
 #pragma unroll
-        for (int j = 0; j < M; ++j) psi[base + da.offs[j]] = cmul(da.fac[j], v[j]);
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < M; ++j)
+                if (live[u]) v[u][j] = psi[base[u] + da.offs[j]];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < M; ++j)
+                if (live[u]) psi[base[u] + da.offs[j]] = cmul(da.fac[j], v[u][j]);
     }
 }
 
 template <typename C, int M>
 __global__ void __launch_bounds__(256) k_perm(C *__restrict__ psi, GroupArgs ga, PermArgs<C, M> pa) {
+    constexpr int U = Unroll<M>::U;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ga.ngroups; g += stride) {
-        const uint64_t base = group_base(g, ga);
-        C v[M];
+    for (uint64_t g0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < ga.ngroups; g0 += U * stride) {
+        uint64_t base[U];
+        bool live[U];
+        C v[U][M];
 #pragma unroll
-        for (int j = 0; j < M; ++j) v[j] = psi[base + pa.src[j]];
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-            const C o = ((pa.one >> j) & 1) ? v[j] : cmul(pa.fac[j], v[j]);
-            psi[base + pa.offs[j]] = o;
+        for (int u = 0; u < U; ++u) {
+            const uint64_t g = g0 + u * stride;
+            live[u] = g < ga.ngroups;
+            base[u] = live[u] ? group_base(g, ga) : 0;
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < M; ++j)
+                if (live[u]) v[u][j] = psi[base[u] + pa.src[j]];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                if (!live[u]) continue;
+                const C o = ((pa.one >> j) & 1) ? v[u][j] : cmul(pa.fac[j], v[u][j]);
+                psi[base[u] + pa.offs[j]] = o;
+            }
     }
 }
 
@@ -135,43 +182,54 @@ template <typename C> __device__ inline C shfl_xor_c(C v, int lanemask) {
 template <typename C, int VEC>
 __global__ void __launch_bounds__(256) k_low1(C *__restrict__ psi, Low1Args<C> a) {
     constexpr int LV = (VEC == 1) ? 0 : (VEC == 2) ? 1 : 2;
+    constexpr int U = 4;   // vectors per lane per iteration, all loaded before use
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    // every lane of a wave runs the same number of iterations: nvec is a
-    // multiple of 64 (the state has at least 64 * VEC amplitudes)
-    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.nvec; w += stride) {
-        const uint64_t i0 = w * VEC;
-        C v[VEC];
+    // nvec is a multiple of 64 and stride of 256, so a wave's lanes are all
+    // live or all idle for every u: the shuffles below see a full wave
+    for (uint64_t w0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w0 < a.nvec; w0 += U * stride) {
+        C v[U][VEC];
 #pragma unroll
-        for (int j = 0; j < VEC; ++j) v[j] = psi[i0 + j];
-        C o[VEC];
-        if (a.t < LV) {
-            const int tb = 1 << a.t;
+        for (int u = 0; u < U; ++u) {
+            const uint64_t w = w0 + u * stride;
+            if (w < a.nvec)
 #pragma unroll
-            for (int j = 0; j < VEC; ++j) {
-                const int b = (j & tb) ? 1 : 0;
-                const C p0 = b ? v[j ^ tb] : v[j];
-                const C p1 = b ? v[j] : v[j ^ tb];
-                C acc = cmul(b ? a.g10 : a.g00, p0);
-                acc = cfma(b ? a.g11 : a.g01, p1, acc);
-                o[j] = acc;
-            }
-        } else {
-            const int lm = 1 << (a.t - LV);
-            const int b = (threadIdx.x & lm) ? 1 : 0;
-#pragma unroll
-            for (int j = 0; j < VEC; ++j) {
-                const C q = shfl_xor_c(v[j], lm);
-                const C p0 = b ? q : v[j];
-                const C p1 = b ? v[j] : q;
-                C acc = cmul(b ? a.g10 : a.g00, p0);
-                acc = cfma(b ? a.g11 : a.g01, p1, acc);
-                o[j] = acc;
-            }
+                for (int j = 0; j < VEC; ++j) v[u][j] = psi[w * VEC + j];
         }
 #pragma unroll
-        for (int j = 0; j < VEC; ++j) {
-            const bool on = ((i0 + j) & a.cmask) == a.cmask;
-            psi[i0 + j] = on ? o[j] : v[j];
+        for (int u = 0; u < U; ++u) {
+            const uint64_t w = w0 + u * stride;
+            if (w >= a.nvec) continue;
+            const uint64_t i0 = w * VEC;
+            C o[VEC];
+            if (a.t < LV) {
+                const int tb = 1 << a.t;
+#pragma unroll
+                for (int j = 0; j < VEC; ++j) {
+                    const int b = (j & tb) ? 1 : 0;
+                    const C p0 = b ? v[u][j ^ tb] : v[u][j];
+                    const C p1 = b ? v[u][j] : v[u][j ^ tb];
+                    C acc = cmul(b ? a.g10 : a.g00, p0);
+                    acc = cfma(b ? a.g11 : a.g01, p1, acc);
+                    o[j] = acc;
+                }
+            } else {
+                const int lm = 1 << (a.t - LV);
+                const int b = (threadIdx.x & lm) ? 1 : 0;
+#pragma unroll
+                for (int j = 0; j < VEC; ++j) {
+                    const C q = shfl_xor_c(v[u][j], lm);
+                    const C p0 = b ? q : v[u][j];
+                    const C p1 = b ? v[u][j] : q;
+                    C acc = cmul(b ? a.g10 : a.g00, p0);
+                    acc = cfma(b ? a.g11 : a.g01, p1, acc);
+                    o[j] = acc;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                const bool on = ((i0 + j) & a.cmask) == a.cmask;
+                psi[i0 + j] = on ? o[j] : v[u][j];
+            }
         }
     }
 }

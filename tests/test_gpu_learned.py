@@ -1,0 +1,71 @@
+"""Learned plan choice: a cost model trained on timings the simulator records
+itself, judged by measured plan time against greedy fusion (the method
+without it) and by an exact state match against the unfused run."""
+import os
+
+import numpy as np
+import pytest
+
+import paper_2203_08826_amd as qsv
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def trained(gpu):
+    from paper_2203_08826_amd import cost_model as CM
+    circs = CM.training_circuits(ns=(20, 22), seed=5)
+    X, y, meta = CM.record(circs, dtypes=(qsv.QSV_C64,), max_ops=12)
+    params, mean, scale, mse = CM.train(X, y, steps=1500)
+    pred = CM.predict(params, mean, scale, X)
+    qsv.qsv_cost_model_set(params, CM.SIZES, mean, scale)
+    yield {"mse": mse, "fit_err": float(np.median(np.abs(np.exp(pred - y) - 1)))}
+    qsv.qsv_cost_model_clear()
+
+
+def _time(plan, st, reps=3):
+    import time
+    import torch
+    qsv.qsv_plan_execute(plan, st)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        qsv.qsv_plan_execute(plan, st)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def test_model_fits_its_training_data(trained):
+    assert trained["mse"] < 0.5
+    assert trained["fit_err"] < 0.5
+
+
+@pytest.mark.parametrize("name", ["qft", "supremacy"])
+def test_learned_beats_greedy_and_matches_unfused(trained, name):
+    import torch
+    n = 24
+    circ = W.qft(n) if name == "qft" else W.supremacy(n, 12, seed=9)
+    psi0 = W.random_state(n, 3)
+    learned = qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_LEARNED, kmax=2)
+    greedy = qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_GREEDY, kmax=2)
+    plain = qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_PER_GATE)
+    ls = learned.stats()
+    assert ls["predicted_s"] > 0
+    a = torch.from_numpy(psi0).to(torch.complex64).cuda()
+    b = a.clone()
+    qsv.qsv_plan_execute(learned, a)
+    qsv.qsv_plan_execute(plain, b)
+    torch.cuda.synchronize()
+    x, y = a.cpu().numpy().astype(np.complex128), b.cpu().numpy().astype(np.complex128)
+    assert np.max(np.abs(x - y)) <= 1e-5
+    infid = 1 - abs(np.vdot(y, x)) ** 2 / (np.vdot(x, x).real * np.vdot(y, y).real)
+    assert infid <= 1e-6
+    st = torch.from_numpy(psi0).to(torch.complex64).cuda()
+    t_learned = _time(learned, st)
+    t_greedy = _time(greedy, st)
+    print("%s n=%d learned mode=%d %.4f s (pred %.4f) greedy %.4f s" % (name, n, ls["mode_used"], t_learned,
+                                                                        ls["predicted_s"], t_greedy))
+    assert t_learned <= 1.05 * t_greedy
