@@ -37,7 +37,27 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-gates", type=int, default=4, help="oracle sample: first gates of the circuit")
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_2203_08826_amd", "cost_model.npz"))
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only time a plain device copy of 2^n complex64 (HBM ceiling and counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration(n, steps):
+    """Device-to-device copy of a 2^n complex64 array: the measured HBM
+    ceiling, and the reference kernel for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    a = torch.randn(1 << n, dtype=torch.complex64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    nbytes = 2 * a.numel() * 8
+    print(json.dumps({"copy_bytes_per_launch": nbytes, "read_bytes": nbytes // 2, "write_bytes": nbytes // 2,
+                      "s": dt, "GB/s": round(nbytes / dt / 1e9, 1)}), flush=True)
 
 
 def main():
@@ -52,6 +72,10 @@ def main():
 
     import paper_2203_08826_amd as qsv
     import workloads as W
+
+    if args.copy_calibration:
+        copy_calibration(args.n, args.steps)
+        return
 
     dev = torch.device("cuda:0")
     n = args.n

@@ -103,10 +103,6 @@ __device__ __forceinline__ void g2(C *v, const R *m, uint32_t cj, bool tok) {
     }
 }
 
-template <typename C, typename R, int NR, int RB, int I>
-__device__ __forceinline__ void pre_phase(C *v, const PassOpDev &op, const PassTermDev *terms, const R *pool,
-                                          uint32_t t, uint64_t base);
-
 template <typename C, typename R, int NR, int RB>
 __device__ __forceinline__ void dispatch_g1(const PassOpDev &op, bool real, C *v, const R *pool,
                                             const PassTermDev *terms, uint32_t t, uint64_t base, bool tok) {
@@ -114,7 +110,6 @@ __device__ __forceinline__ void dispatch_g1(const PassOpDev &op, bool real, C *v
 #define QSV_G1(I)                                                               \
     case I:                                                                     \
         if constexpr (I < RB) {                                                 \
-            if (op.pre) pre_phase<C, R, NR, RB, I>(v, op, terms, pool, t, base); \
             if (real) g1r<C, R, NR, I>(v, m, op.cj, tok);                       \
             else g1<C, R, NR, I>(v, m, op.cj, tok);                             \
         }                                                                       \
@@ -180,14 +175,17 @@ __device__ __forceinline__ void phase_table(C *f, const PassOpDev &op, const Pas
     constexpr int NQ = RB * (RB - 1) / 2;
     auto sum_group = [&](int g) -> uint64_t {
         // chunk-only terms first: every operand is wave-uniform (scalar unit)
+        // (unrolled so that several term loads are in flight at once)
         uint64_t su = 0;
         const int u = op.grpu[g];
+#pragma unroll 8
         for (int k = op.grp[g]; k < u; ++k) {
             const PassTermDev tm = terms[k];
             su += ((base & tm.mn) == tm.mn) ? tm.theta : 0ull;
         }
         uint64_t s = 0;
         const int e = op.grp[g + 1];
+#pragma unroll 8
         for (int k = u; k < e; ++k) {
             const PassTermDev tm = terms[k];
             const bool ok = ((t & tm.mt) == tm.mt) && ((base & tm.mn) == tm.mn);
@@ -248,33 +246,6 @@ __device__ __forceinline__ void phase_op(C *v, const PassOpDev &op, const PassTe
             x = rot(x, ph);
         }
         v[j] = x;
-    }
-}
-
-// The phase that precedes a one-qubit gate on register bit I multiplies only
-// its |1> members: apply it to v[j | 2^I] for every j with bit I clear.
-template <typename C, typename R, int NR, int RB, int I>
-__device__ __forceinline__ void pre_phase(C *v, const PassOpDev &op, const PassTermDev *terms, const R *pool,
-                                          uint32_t t, uint64_t base) {
-    constexpr int NQ = RB * (RB - 1) / 2;
-    C f[NR];
-    phase_table<C, R, NR, RB, I>(f, op, terms, pool, t, base);
-    const int gen_b = op.grp[1 + RB + NQ], gen_e = op.grp[2 + RB + NQ];
-#pragma unroll
-    for (int j = 0; j < NR; ++j) {
-        if ((j >> I) & 1) continue;
-        C x = cmul(v[j | (1 << I)], f[j]);
-        if (gen_e > gen_b) {
-            uint64_t ph = 0;
-            for (int k = gen_b; k < gen_e; ++k) {
-                const PassTermDev tm = terms[k];
-                const bool ok =
-                    ((t & tm.mt) == tm.mt) && ((base & tm.mn) == tm.mn) && (((uint32_t)j & tm.mj) == tm.mj);
-                ph += ok ? tm.theta : 0ull;
-            }
-            x = rot(x, ph);
-        }
-        v[j | (1 << I)] = x;
     }
 }
 

@@ -340,8 +340,14 @@ int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> 
             if (op.lt.size() == 1) {
                 d.a = reg_index(cur, op.lt[0]);
                 if (!op.pre.empty()) {
-                    d.pre = 1;
-                    encode_terms(op.pre, op.lt[0], d);
+                    // the phase terms that must precede this gate all contain its
+                    // target: a PHASE op under the same partition (its factor is 1
+                    // wherever the target bit is 0)
+                    PassOpDev ph;
+                    std::memset(&ph, 0, sizeof(ph));
+                    ph.kind = POP_PHASE;
+                    encode_terms(op.pre, -1, ph);
+                    prog.ops.push_back(ph);
                 }
                 d.mat = (int)prog.pool.size();
                 bool real = true;

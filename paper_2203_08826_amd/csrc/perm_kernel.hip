@@ -37,10 +37,36 @@ __device__ __forceinline__ uint64_t bp_permute_global(uint64_t x, const BitPermA
 template <typename C>
 __global__ void __launch_bounds__(BP_THREADS) k_bitperm(C *__restrict__ psi, BitPermArgs a) {
     __shared__ C buf[2][1 << (BP_MAX_L - (sizeof(C) == 16 ? 1 : 0))];
+    // scatter tables: local index l = (hi << 6) | lo -> global offset, and the
+    // local permutation, split in 6-bit halves
+    __shared__ uint64_t sc_lo[64], sc_hi[64];
+    __shared__ uint32_t lm_lo[64], lm_hi[64];
     const uint64_t c = blockIdx.x;
-    if (c >= a.nchunks) return;
     const int L = a.L;
     const uint32_t csize = 1u << L;
+    if (threadIdx.x < 64) {
+        const uint32_t x = threadIdx.x;
+        uint64_t slo = 0, shi = 0;
+        uint32_t mlo = 0, mhi = 0;
+        for (int i = 0; i < L; ++i) {
+            const int src_bit = i < 6 ? i : i - 6;
+            const bool bit = (x >> src_bit) & 1;
+            if (!bit) continue;
+            if (i < 6) {
+                slo |= 1ull << a.lpos[i];
+                mlo |= 1u << a.lperm[i];
+            } else if (i < 12) {
+                shi |= 1ull << a.lpos[i];
+                mhi |= 1u << a.lperm[i];
+            }
+        }
+        sc_lo[x] = slo;
+        sc_hi[x] = shi;
+        lm_lo[x] = mlo;
+        lm_hi[x] = mhi;
+    }
+    __syncthreads();
+    if (c >= a.nchunks) return;
     // chunk base from the chunk index, then its partner under sigma
     uint64_t base = c;
     for (int b = 0; b < L; ++b) {
@@ -63,29 +89,20 @@ __global__ void __launch_bounds__(BP_THREADS) k_bitperm(C *__restrict__ psi, Bit
     }
     if (pc < c) return;   // the partner's workgroup moves this pair
     const bool pair = pc != c;
-    auto gaddr = [&](uint64_t cb, uint32_t l) {
-        uint64_t g = cb;
-        for (int i = 0; i < L; ++i)
-            if ((l >> i) & 1) g |= 1ull << a.lpos[i];
-        return g;
-    };
-    auto lmap = [&](uint32_t l) {
-        uint32_t r = 0;
-        for (int i = 0; i < L; ++i)
-            if ((l >> i) & 1) r |= 1u << a.lperm[i];
-        return r;
-    };
     for (uint32_t l = threadIdx.x; l < csize; l += BP_THREADS) {
-        buf[0][bp_swz(l)] = psi[gaddr(base, l)];
-        if (pair) buf[1][bp_swz(l)] = psi[gaddr(pbase, l)];
+        const uint64_t off = sc_lo[l & 63] | sc_hi[l >> 6];
+        buf[0][bp_swz(l)] = psi[base | off];
+        if (pair) buf[1][bp_swz(l)] = psi[pbase | off];
     }
     __syncthreads();
     // element l of chunk c lands at local position lmap(l) of chunk sigma(c):
-    // write every output position in order, reading its source
+    // write every output position in order, reading its source (sigma is an
+    // involution, so the source of lo is lmap(lo))
     for (uint32_t lo = threadIdx.x; lo < csize; lo += BP_THREADS) {
-        const uint32_t li = lmap(lo);   // sigma is an involution
-        psi[gaddr(pbase, lo)] = buf[0][bp_swz(li)];
-        if (pair) psi[gaddr(base, lo)] = buf[1][bp_swz(li)];
+        const uint64_t off = sc_lo[lo & 63] | sc_hi[lo >> 6];
+        const uint32_t li = lm_lo[lo & 63] | lm_hi[lo >> 6];
+        psi[pbase | off] = buf[0][bp_swz(li)];
+        if (pair) psi[base | off] = buf[1][bp_swz(li)];
     }
 }
 
