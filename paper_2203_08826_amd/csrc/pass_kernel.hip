@@ -104,12 +104,28 @@ __device__ __forceinline__ void g2(C *v, const R *m, uint32_t cj, bool tok) {
 }
 
 template <typename C, typename R, int NR, int RB>
+__device__ void full_phase_table(C *f, const PassOpDev &op, const PassTermDev *terms, const R *pool, uint32_t t,
+                                 uint64_t base);
+
+// The phase that precedes a one-qubit gate on register bit I multiplies only
+// its |1> members; its terms never need bit I, so f[j] = f[j | 2^I].
+template <typename C, int NR, int I>
+__device__ __forceinline__ void apply_pre(C *v, const C *f) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+        if (!((j >> I) & 1)) v[j | (1 << I)] = cmul(v[j | (1 << I)], f[j]);
+}
+
+template <typename C, typename R, int NR, int RB>
 __device__ __forceinline__ void dispatch_g1(const PassOpDev &op, bool real, C *v, const R *pool,
                                             const PassTermDev *terms, uint32_t t, uint64_t base, bool tok) {
     const R *m = pool + op.mat;
+    C f[NR];
+    if (op.pre) full_phase_table<C, R, NR, RB>(f, op, terms, pool, t, base);
 #define QSV_G1(I)                                                               \
     case I:                                                                     \
         if constexpr (I < RB) {                                                 \
+            if (op.pre) apply_pre<C, NR, I>(v, f);                              \
             if (real) g1r<C, R, NR, I>(v, m, op.cj, tok);                       \
             else g1<C, R, NR, I>(v, m, op.cj, tok);                             \
         }                                                                       \
@@ -178,14 +194,14 @@ __device__ __forceinline__ void phase_table(C *f, const PassOpDev &op, const Pas
         // (unrolled so that several term loads are in flight at once)
         uint64_t su = 0;
         const int u = op.grpu[g];
-#pragma unroll 8
+#pragma unroll 4
         for (int k = op.grp[g]; k < u; ++k) {
             const PassTermDev tm = terms[k];
             su += ((base & tm.mn) == tm.mn) ? tm.theta : 0ull;
         }
         uint64_t s = 0;
         const int e = op.grp[g + 1];
-#pragma unroll 8
+#pragma unroll 4
         for (int k = u; k < e; ++k) {
             const PassTermDev tm = terms[k];
             const bool ok = ((t & tm.mt) == tm.mt) && ((base & tm.mn) == tm.mn);
@@ -197,9 +213,17 @@ __device__ __forceinline__ void phase_table(C *f, const PassOpDev &op, const Pas
     one.x = 1;
     one.y = 0;
     f[0] = (op.grp[1] > op.grp[0]) ? expi(sum_group(0), R()) : one;
+    // single-bit factors: a host constant times the per-thread part (if any)
     C E[RB];
 #pragma unroll
-    for (int i = 0; i < RB; ++i) E[i] = (i != SKIP && op.grp[2 + i] > op.grp[1 + i]) ? expi(sum_group(1 + i), R()) : one;
+    for (int i = 0; i < RB; ++i) {
+        if (i == SKIP) continue;
+        C e;
+        e.x = pool[op.lf + 2 * i];
+        e.y = pool[op.lf + 2 * i + 1];
+        if (op.grp[2 + i] > op.grp[1 + i]) e = cmul(e, expi(sum_group(1 + i), R()));
+        E[i] = e;
+    }
     C Q[NQ > 0 ? NQ : 1];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -225,17 +249,18 @@ __device__ __forceinline__ void phase_table(C *f, const PassOpDev &op, const Pas
     }
 }
 
+// Complete factor table of a grouped phase, including the terms of the last
+// group (evaluated per register index).  One copy of this code serves every
+// PHASE op and every pre-phased one-qubit gate.
 template <typename C, typename R, int NR, int RB>
-__device__ __forceinline__ void phase_op(C *v, const PassOpDev &op, const PassTermDev *terms, const R *pool,
-                                         uint32_t t, uint64_t base) {
+__device__ void full_phase_table(C *f, const PassOpDev &op, const PassTermDev *terms, const R *pool, uint32_t t,
+                                 uint64_t base) {
     constexpr int NQ = RB * (RB - 1) / 2;
-    C f[NR];
     phase_table<C, R, NR, RB, -1>(f, op, terms, pool, t, base);
     const int gen_b = op.grp[1 + RB + NQ], gen_e = op.grp[2 + RB + NQ];
+    if (gen_e > gen_b) {
 #pragma unroll
-    for (int j = 0; j < NR; ++j) {
-        C x = cmul(v[j], f[j]);
-        if (gen_e > gen_b) {
+        for (int j = 0; j < NR; ++j) {
             uint64_t ph = 0;
             for (int k = gen_b; k < gen_e; ++k) {
                 const PassTermDev tm = terms[k];
@@ -243,10 +268,18 @@ __device__ __forceinline__ void phase_op(C *v, const PassOpDev &op, const PassTe
                     ((t & tm.mt) == tm.mt) && ((base & tm.mn) == tm.mn) && (((uint32_t)j & tm.mj) == tm.mj);
                 ph += ok ? tm.theta : 0ull;
             }
-            x = rot(x, ph);
+            f[j] = rot(f[j], ph);
         }
-        v[j] = x;
     }
+}
+
+template <typename C, typename R, int NR, int RB>
+__device__ __forceinline__ void phase_op(C *v, const PassOpDev &op, const PassTermDev *terms, const R *pool,
+                                         uint32_t t, uint64_t base) {
+    C f[NR];
+    full_phase_table<C, R, NR, RB>(f, op, terms, pool, t, base);
+#pragma unroll
+    for (int j = 0; j < NR; ++j) v[j] = cmul(v[j], f[j]);
 }
 
 template <typename R, int RB>

@@ -270,7 +270,7 @@ int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> 
     auto encode_terms = [&](const std::vector<std::pair<uint64_t, std::pair<uint32_t, uint64_t>>> &terms, int skip,
                             PassOpDev &d) {
         std::vector<std::vector<PassTermDev>> groups(ngroups);
-        std::vector<uint64_t> qconst(NQ > 0 ? NQ : 1, 0);
+        std::vector<uint64_t> qconst(NQ > 0 ? NQ : 1, 0), lconst(RB, 0);
         for (auto &t : terms) {
             PassTermDev td;
             std::memset(&td, 0, sizeof(td));
@@ -289,7 +289,10 @@ int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> 
             }
             int gidx;
             if (regs.empty()) gidx = 0;
-            else if (regs.size() == 1) gidx = 1 + regs[0];
+            else if (regs.size() == 1 && td.mt == 0 && td.mn == 0) {
+                lconst[regs[0]] += td.theta;   // constant: folded into a host factor
+                continue;
+            } else if (regs.size() == 1) gidx = 1 + regs[0];
             else if (regs.size() == 2 && td.mt == 0 && td.mn == 0) {
                 const int a = std::max(regs[0], regs[1]), b = std::min(regs[0], regs[1]);
                 qconst[a * (a - 1) / 2 + b] += td.theta;   // constant: folded into a host factor
@@ -312,6 +315,12 @@ int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> 
         d.qf = (int)prog.pool.size();
         for (int q = 0; q < NQ; ++q) {
             const double ang = 2.0 * M_PI * ((double)(int64_t)qconst[q] * 5.421010862427522e-20);
+            prog.pool.push_back(std::cos(ang));
+            prog.pool.push_back(std::sin(ang));
+        }
+        d.lf = (int)prog.pool.size();
+        for (int i = 0; i < RB; ++i) {
+            const double ang = 2.0 * M_PI * ((double)(int64_t)lconst[i] * 5.421010862427522e-20);
             prog.pool.push_back(std::cos(ang));
             prog.pool.push_back(std::sin(ang));
         }
@@ -341,13 +350,10 @@ int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> 
                 d.a = reg_index(cur, op.lt[0]);
                 if (!op.pre.empty()) {
                     // the phase terms that must precede this gate all contain its
-                    // target: a PHASE op under the same partition (its factor is 1
-                    // wherever the target bit is 0)
-                    PassOpDev ph;
-                    std::memset(&ph, 0, sizeof(ph));
-                    ph.kind = POP_PHASE;
-                    encode_terms(op.pre, -1, ph);
-                    prog.ops.push_back(ph);
+                    // target: applied to the gate's |1> members, grouped by the
+                    // other bits they need
+                    d.pre = 1;
+                    encode_terms(op.pre, op.lt[0], d);
                 }
                 d.mat = (int)prog.pool.size();
                 bool real = true;

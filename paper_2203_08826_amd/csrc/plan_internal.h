@@ -50,6 +50,7 @@ struct PassOpDev {
     int32_t grp[PASS_GROUPS + 1];   // term ranges [grp[g], grp[g+1]) per group
     int32_t grpu[PASS_GROUPS];      // terms [grp[g], grpu[g]) need no thread bit (uniform per chunk)
     int32_t qf;            // pool offset of the constant pair factors (complex, one per pair)
+    int32_t lf;            // pool offset of the constant single-bit factors (complex, one per register bit)
     int32_t pre;           // G1/G1R: apply the grouped phase to the |1> member first
 };
 
