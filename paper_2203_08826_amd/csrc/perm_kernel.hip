@@ -89,20 +89,40 @@ __global__ void __launch_bounds__(BP_THREADS) k_bitperm(C *__restrict__ psi, Bit
     }
     if (pc < c) return;   // the partner's workgroup moves this pair
     const bool pair = pc != c;
-    for (uint32_t l = threadIdx.x; l < csize; l += BP_THREADS) {
-        const uint64_t off = sc_lo[l & 63] | sc_hi[l >> 6];
-        buf[0][bp_swz(l)] = psi[base | off];
-        if (pair) buf[1][bp_swz(l)] = psi[pbase | off];
+    // fixed trip count (the largest chunk) so that all loads are issued
+    // before the first LDS store
+    constexpr int IT = (1 << (BP_MAX_L - (sizeof(C) == 16 ? 1 : 0))) / BP_THREADS;
+    C r0[IT], r1[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const uint32_t l = threadIdx.x + i * BP_THREADS;
+        if (l < csize) {
+            const uint64_t off = sc_lo[l & 63] | sc_hi[l >> 6];
+            r0[i] = psi[base | off];
+            if (pair) r1[i] = psi[pbase | off];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const uint32_t l = threadIdx.x + i * BP_THREADS;
+        if (l < csize) {
+            buf[0][bp_swz(l)] = r0[i];
+            if (pair) buf[1][bp_swz(l)] = r1[i];
+        }
     }
     __syncthreads();
     // element l of chunk c lands at local position lmap(l) of chunk sigma(c):
     // write every output position in order, reading its source (sigma is an
     // involution, so the source of lo is lmap(lo))
-    for (uint32_t lo = threadIdx.x; lo < csize; lo += BP_THREADS) {
-        const uint64_t off = sc_lo[lo & 63] | sc_hi[lo >> 6];
-        const uint32_t li = lm_lo[lo & 63] | lm_hi[lo >> 6];
-        psi[pbase | off] = buf[0][bp_swz(li)];
-        if (pair) psi[base | off] = buf[1][bp_swz(li)];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const uint32_t lo = threadIdx.x + i * BP_THREADS;
+        if (lo < csize) {
+            const uint64_t off = sc_lo[lo & 63] | sc_hi[lo >> 6];
+            const uint32_t li = lm_lo[lo & 63] | lm_hi[lo >> 6];
+            psi[pbase | off] = buf[0][bp_swz(li)];
+            if (pair) psi[base | off] = buf[1][bp_swz(li)];
+        }
     }
 }
 
