@@ -172,6 +172,15 @@ def expval_tfim(state, J=1.0, h=0.5, periodic=False):
     return float(np.vdot(state, apply_h_tfim(state, J, h, periodic)).real)
 
 
+def qft_basis_amplitudes(n, x, ys):
+    """Amplitudes <y|QFT|x> = e^{2 pi i x y / 2^n} / 2^{n/2} for the sampled
+    outputs ys (closed form of the quantum Fourier transform; the phase is
+    reduced exactly in integers before the float conversion)."""
+    ys = np.asarray(ys, dtype=np.int64)
+    frac = ((int(x) * ys) % (1 << n)).astype(np.float64) / float(1 << n)
+    return np.exp(2j * np.pi * frac) / 2.0 ** (n / 2.0)
+
+
 # ---------------------------------------------------------------- Kronecker checker
 
 def kron_operator(n, G, targets, controls=()):

@@ -134,6 +134,15 @@ def test_qft_basis_state_closed_form():
     assert np.max(np.abs(out - want)) <= 1e-13
 
 
+def test_qft_closed_form_sampler_matches_eq1():
+    # the sampled closed form used at 30 qubits equals the Eq. 1 run at 13
+    n = 13
+    x = W.basis_index(n, 4)
+    full = S.run_circuit(S.basis_state(n, x), W.qft(n))
+    ys = np.random.default_rng(2).integers(0, 1 << n, size=500)
+    assert np.max(np.abs(S.qft_basis_amplitudes(n, x, ys) - full[ys])) <= 1e-13
+
+
 def test_qft_planted_sign_error_is_caught():
     n = 8
     circ = W.qft(n)
