@@ -24,6 +24,14 @@ namespace qsv {
 
 constexpr int PT = 256;
 
+// Workgroup barrier that orders LDS accesses only: outstanding global loads
+// (the next chunk's prefetch) stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ uint32_t lds_swizzle(uint32_t l) {
     return l ^ (((l >> 4) ^ (l >> 8) ^ (l >> 12)) & 15u);
 }
@@ -298,33 +306,47 @@ __global__ void __launch_bounds__(PT) k_pass(typename cplx_of<R>::type *__restri
     const uint32_t t = threadIdx.x;
     const int nops = H->nops;
 
-    for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    auto chunk_base = [&](uint64_t c) {
         uint64_t base = c;
 #pragma unroll
         for (int b = 0; b < L; ++b) {
             const uint64_t lo = base & H->lowmask[b];
             base = lo | ((base ^ lo) << 1);
         }
-        C v[NR];
-        int cur = H->load_part;
-        {
-            const PassPartition &P = parts[cur];
-            uint64_t gt = base;
+        return base;
+    };
+    // register offsets of the load partition (the same for every chunk)
+    uint64_t lt_in = 0, lr_in[RB];
+    {
+        const PassPartition &P = parts[H->load_part];
 #pragma unroll
-            for (int u = 0; u < PASS_THREAD_BITS; ++u)
-                if ((t >> u) & 1) gt |= 1ull << H->in_pos[P.thr_l[u]];
-            uint64_t gr[RB];
+        for (int u = 0; u < PASS_THREAD_BITS; ++u)
+            if ((t >> u) & 1) lt_in |= 1ull << H->in_pos[P.thr_l[u]];
 #pragma unroll
-            for (int i = 0; i < RB; ++i) gr[i] = 1ull << H->in_pos[P.reg_l[i]];
+        for (int i = 0; i < RB; ++i) lr_in[i] = 1ull << H->in_pos[P.reg_l[i]];
+    }
+    auto load_chunk = [&](C *dst, uint64_t base) {
 #pragma unroll
-            for (int j = 0; j < NR; ++j) {
-                uint64_t g = gt;
+        for (int j = 0; j < NR; ++j) {
+            uint64_t g = base | lt_in;
 #pragma unroll
-                for (int i = 0; i < RB; ++i)
-                    if ((j >> i) & 1) g |= gr[i];
-                v[j] = psi[g];
-            }
+            for (int i = 0; i < RB; ++i)
+                if ((j >> i) & 1) g |= lr_in[i];
+            dst[j] = psi[g];
         }
+    };
+    // Software pipeline: the next chunk's loads are issued before the
+    // current chunk is computed, and the barriers below order LDS traffic
+    // only, so those loads stay in flight across them.
+    uint64_t c = blockIdx.x;
+    C v[NR];
+    if (c < nchunks) load_chunk(v, chunk_base(c));
+    for (; c < nchunks; c += gridDim.x) {
+        const uint64_t base = chunk_base(c);
+        const uint64_t cn = c + gridDim.x;
+        C vn[NR];
+        if (cn < nchunks) load_chunk(vn, chunk_base(cn));
+        int cur = H->load_part;
         for (int o = 0; o < nops; ++o) {
             const PassOpDev &op = ops[o];
             const bool tok = ((t & op.ct) == op.ct) && ((base & op.cn) == op.cn);
@@ -344,7 +366,7 @@ __global__ void __launch_bounds__(PT) k_pass(typename cplx_of<R>::type *__restri
                         lq |= 1u << Q.thr_l[u];
                     }
                 }
-                __syncthreads();
+                lds_barrier();
 #pragma unroll
                 for (int j = 0; j < NR; ++j) {
                     uint32_t l = lt;
@@ -353,7 +375,7 @@ __global__ void __launch_bounds__(PT) k_pass(typename cplx_of<R>::type *__restri
                         if ((j >> i) & 1) l |= 1u << P.reg_l[i];
                     lds[lds_swizzle(l)] = v[j];
                 }
-                __syncthreads();
+                lds_barrier();
 #pragma unroll
                 for (int j = 0; j < NR; ++j) {
                     uint32_t l = lq;
@@ -370,8 +392,9 @@ __global__ void __launch_bounds__(PT) k_pass(typename cplx_of<R>::type *__restri
         }
         {
             // A thread may store to addresses another thread of the chunk
-            // loaded (relabelled local bits, or a partition change without
-            // an exchange in between): every load of the chunk must be done.
+            // loaded (relabelled local bits without an exchange in between):
+            // every load of the chunk must be done (a full barrier waits for
+            // all of this wave's outstanding loads).
             if (H->relabel) __syncthreads();
             const PassPartition &P = parts[cur];
             uint64_t gt = base;
@@ -390,6 +413,8 @@ __global__ void __launch_bounds__(PT) k_pass(typename cplx_of<R>::type *__restri
                 psi[g] = v[j];
             }
         }
+#pragma unroll
+        for (int j = 0; j < NR; ++j) v[j] = vn[j];
     }
 }
 
@@ -431,8 +456,20 @@ void PassProgram::serialise() {
 
 template <typename R, int RB>
 static void launch_k_pass(void *state, const uint8_t *dprog, uint64_t nchunks, hipStream_t s) {
-    uint64_t g = nchunks;
-    if (g > (1ull << 20)) g = 1ull << 20;
+    // persistent workgroups: as many as can be resident, each walking the
+    // chunks with a stride (so its prefetch always has a next chunk)
+    static int resident[64] = {0};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev < 0 || dev >= 64) dev = 0;
+    if (resident[dev] == 0) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pass<R, RB>, PT, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        resident[dev] = per_cu;
+    }
+    uint64_t g = (uint64_t)resident[dev] * device_sm_count();
+    if (g > nchunks) g = nchunks;
     hipLaunchKernelGGL((k_pass<R, RB>), dim3((unsigned)g), dim3(PT), 0, s, (typename cplx_of<R>::type *)state, dprog,
                        nchunks);
 }
