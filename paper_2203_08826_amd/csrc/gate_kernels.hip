@@ -59,102 +59,116 @@ __device__ inline uint64_t group_base(uint64_t g, const GroupArgs &ga) {
     return i | ga.cmask;
 }
 
-// Groups per thread per loop iteration: several independent groups keep
-// enough loads in flight to cover HBM latency when a group is small.
+// Work per thread per loop iteration: U units of VG consecutive groups.
+// Several independent units keep enough loads in flight to cover HBM latency
+// when a group is small; when bit 0 is not a gate bit, VG = 2 consecutive
+// groups are adjacent in memory and each member access is a 16-byte (c64) or
+// 32-byte (c128) vector.
 template <int M> struct Unroll { static constexpr int U = M <= 2 ? 4 : (M <= 4 ? 2 : 1); };
 
-template <typename C, int M>
+template <int U, int VG>
+__device__ __forceinline__ void unit_bases(uint64_t w0, uint64_t wstride, uint64_t nunits, const GroupArgs &ga,
+                                           uint64_t *base, bool *live) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint64_t w = w0 + u * wstride;
+        live[u] = w < nunits;
+        base[u] = live[u] ? group_base(w * VG, ga) : 0;   // + r for the r-th group of the unit
+    }
+}
+
+template <typename C, int M, int VG>
 __global__ void __launch_bounds__(256) k_dense(C *__restrict__ psi, GroupArgs ga, DenseArgs<C, M> da) {
     constexpr int U = Unroll<M>::U;
+    const uint64_t nunits = ga.ngroups / VG;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t g0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < ga.ngroups; g0 += U * stride) {
+    for (uint64_t w0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w0 < nunits; w0 += U * stride) {
         uint64_t base[U];
         bool live[U];
-        C v[U][M];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint64_t g = g0 + u * stride;
-            live[u] = g < ga.ngroups;
-            base[u] = live[u] ? group_base(g, ga) : 0;
-        }
+        C v[U][M][VG];
+        unit_bases<U, VG>(w0, stride, nunits, ga, base, live);
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int j = 0; j < M; ++j)
-                if (live[u]) v[u][j] = psi[base[u] + da.offs[j]];
+#pragma unroll
+                for (int r = 0; r < VG; ++r)
+                    if (live[u]) v[u][j][r] = psi[base[u] + da.offs[j] + r];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (!live[u]) continue;
 #pragma unroll
-            for (int r = 0; r < M; ++r) {
-                C acc;
-                acc.x = 0;
-                acc.y = 0;
+            for (int q = 0; q < M; ++q)
 #pragma unroll
-                for (int j = 0; j < M; ++j) {
-                    const C gm = (M <= 8) ? da.mat[r * M + j] : da.dmat[r * M + j];
-                    acc = cfma(gm, v[u][j], acc);
+                for (int r = 0; r < VG; ++r) {
+                    C acc;
+                    acc.x = 0;
+                    acc.y = 0;
+#pragma unroll
+                    for (int j = 0; j < M; ++j) {
+                        const C gm = (M <= 8) ? da.mat[q * M + j] : da.dmat[q * M + j];
+                        acc = cfma(gm, v[u][j][r], acc);
+                    }
+                    psi[base[u] + da.offs[q] + r] = acc;
                 }
-                psi[base[u] + da.offs[r]] = acc;
-            }
         }
     }
 }
 
-template <typename C, int M>
+template <typename C, int M, int VG>
 __global__ void __launch_bounds__(256) k_diag(C *__restrict__ psi, GroupArgs ga, DiagArgs<C, M> da) {
     constexpr int U = Unroll<M>::U;
+    const uint64_t nunits = ga.ngroups / VG;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t g0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < ga.ngroups; g0 += U * stride) {
+    for (uint64_t w0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w0 < nunits; w0 += U * stride) {
         uint64_t base[U];
         bool live[U];
-        C v[U][M];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint64_t g = g0 + u * stride;
-            live[u] = g < ga.ngroups;
-            base[u] = live[u] ? group_base(g, ga) : 0;
-        }
+        C v[U][M][VG];
+        unit_bases<U, VG>(w0, stride, nunits, ga, base, live);
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int j = 0; j < M; ++j)
-                if (live[u]) v[u][j] = psi[base[u] + da.offs[j]];
+#pragma unroll
+                for (int r = 0; r < VG; ++r)
+                    if (live[u]) v[u][j][r] = psi[base[u] + da.offs[j] + r];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int j = 0; j < M; ++j)
-                if (live[u]) psi[base[u] + da.offs[j]] = cmul(da.fac[j], v[u][j]);
+#pragma unroll
+                for (int r = 0; r < VG; ++r)
+                    if (live[u]) psi[base[u] + da.offs[j] + r] = cmul(da.fac[j], v[u][j][r]);
     }
 }
 
-template <typename C, int M>
+template <typename C, int M, int VG>
 __global__ void __launch_bounds__(256) k_perm(C *__restrict__ psi, GroupArgs ga, PermArgs<C, M> pa) {
     constexpr int U = Unroll<M>::U;
+    const uint64_t nunits = ga.ngroups / VG;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t g0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g0 < ga.ngroups; g0 += U * stride) {
+    for (uint64_t w0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w0 < nunits; w0 += U * stride) {
         uint64_t base[U];
         bool live[U];
-        C v[U][M];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint64_t g = g0 + u * stride;
-            live[u] = g < ga.ngroups;
-            base[u] = live[u] ? group_base(g, ga) : 0;
-        }
+        C v[U][M][VG];
+        unit_bases<U, VG>(w0, stride, nunits, ga, base, live);
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int j = 0; j < M; ++j)
-                if (live[u]) v[u][j] = psi[base[u] + pa.src[j]];
+#pragma unroll
+                for (int r = 0; r < VG; ++r)
+                    if (live[u]) v[u][j][r] = psi[base[u] + pa.src[j] + r];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int j = 0; j < M; ++j) {
-                if (!live[u]) continue;
-                const C o = ((pa.one >> j) & 1) ? v[u][j] : cmul(pa.fac[j], v[u][j]);
-                psi[base[u] + pa.offs[j]] = o;
-            }
+            for (int j = 0; j < M; ++j)
+#pragma unroll
+                for (int r = 0; r < VG; ++r) {
+                    if (!live[u]) continue;
+                    const C o = ((pa.one >> j) & 1) ? v[u][j][r] : cmul(pa.fac[j], v[u][j][r]);
+                    psi[base[u] + pa.offs[j] + r] = o;
+                }
     }
 }
 
@@ -254,6 +268,9 @@ static GroupArgs make_group_args(const GateAnalysis &a) {
     return ga;
 }
 
+// two consecutive groups are adjacent amplitudes when bit 0 is no gate bit
+static bool vg2(const GroupArgs &ga) { return ga.ngroups >= 2 && (ga.m == 0 || ga.lowmask[0] != 0); }
+
 template <typename C> static C to_c(const double *z) {
     C r;
     r.x = (decltype(r.x))z[0];
@@ -269,7 +286,8 @@ static void launch_dense_m(C *psi, const GateAnalysis &a, const GroupArgs &ga, c
     if (M <= 8)
         for (int j = 0; j < M * M; ++j) da.mat[j] = to_c<C>(&a.mat[2 * j]);
     da.dmat = dmat;
-    hipLaunchKernelGGL((k_dense<C, M>), dim3(grid_for(ga.ngroups, 256)), dim3(256), 0, s, psi, ga, da);
+    if (vg2(ga)) hipLaunchKernelGGL((k_dense<C, M, 2>), dim3(grid_for(ga.ngroups / 2, 256)), dim3(256), 0, s, psi, ga, da);
+    else hipLaunchKernelGGL((k_dense<C, M, 1>), dim3(grid_for(ga.ngroups, 256)), dim3(256), 0, s, psi, ga, da);
 }
 
 template <typename C, int M>
@@ -280,7 +298,8 @@ static void launch_diag_m(C *psi, const GateAnalysis &a, const GroupArgs &ga, hi
         da.offs[j] = a.offs[j];
         da.fac[j] = to_c<C>(&a.mat[2 * j]);
     }
-    hipLaunchKernelGGL((k_diag<C, M>), dim3(grid_for(ga.ngroups, 256)), dim3(256), 0, s, psi, ga, da);
+    if (vg2(ga)) hipLaunchKernelGGL((k_diag<C, M, 2>), dim3(grid_for(ga.ngroups / 2, 256)), dim3(256), 0, s, psi, ga, da);
+    else hipLaunchKernelGGL((k_diag<C, M, 1>), dim3(grid_for(ga.ngroups, 256)), dim3(256), 0, s, psi, ga, da);
 }
 
 template <typename C, int M>
@@ -293,7 +312,8 @@ static void launch_perm_m(C *psi, const GateAnalysis &a, const GroupArgs &ga, hi
         pa.fac[j] = to_c<C>(&a.mat[2 * j]);
         if (a.perm_one[j]) pa.one |= 1ull << j;
     }
-    hipLaunchKernelGGL((k_perm<C, M>), dim3(grid_for(ga.ngroups, 256)), dim3(256), 0, s, psi, ga, pa);
+    if (vg2(ga)) hipLaunchKernelGGL((k_perm<C, M, 2>), dim3(grid_for(ga.ngroups / 2, 256)), dim3(256), 0, s, psi, ga, pa);
+    else hipLaunchKernelGGL((k_perm<C, M, 1>), dim3(grid_for(ga.ngroups, 256)), dim3(256), 0, s, psi, ga, pa);
 }
 
 // Low-qubit path for a one-target dense gate whose target is below the
