@@ -39,7 +39,177 @@ def parse():
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_2203_08826_amd", "cost_model.npz"))
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only time a plain device copy of 2^n complex64 (HBM ceiling and counter calibration)")
+    ap.add_argument("--workload", default="qft", choices=["qft", "supremacy", "variational", "adjoint", "learned"],
+                    help="qft: the headline line; the others print their own configuration's line")
+    ap.add_argument("--depth", type=int, default=20)
+    ap.add_argument("--layers", type=int, default=40)
     return ap.parse_args()
+
+
+def _timed(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def _zero_state(n, dtype):
+    import torch
+    st = torch.zeros(1 << n, dtype=dtype, device="cuda")
+    st[0] = 1.0
+    return st
+
+
+def _infidelity(qsv, a, b):
+    import torch
+    a = a.to(torch.complex128)
+    b = b.to(torch.complex128)
+    ov = qsv.qsv_inner(a, b).cpu().numpy()
+    na = qsv.qsv_norm2(a).cpu().numpy()[0]
+    nb = qsv.qsv_norm2(b).cpu().numpy()[0]
+    return float(1.0 - (ov[0] ** 2 + ov[1] ** 2) / (na * nb))
+
+
+def workload_supremacy(args):
+    """Random supremacy-like circuit: per-gate kernels vs LDS passes, c64 and c128."""
+    import torch
+    import paper_2203_08826_amd as qsv
+    import workloads as W
+    n = args.n
+    circ = W.supremacy(n, args.depth, seed=0)
+    out = {"metric": "circuit s & HBM GB/s", "config": {"workload": "supremacy-like n=%d depth=%d (%d gates)" % (
+        n, args.depth, len(circ))}, "results": {}}
+    for dname, dt, tdt in (("c64", qsv.QSV_C64, torch.complex64), ("c128", qsv.QSV_C128, torch.complex128)):
+        for pname, mode in (("per_gate", qsv.PLAN_PER_GATE), ("passes", qsv.PLAN_PASSES)):
+            plan = qsv.qsv_plan_create(n, dt, circ, mode=mode)
+            st = _zero_state(n, tdt)
+            s = _timed(lambda: qsv.qsv_plan_execute(plan, st), 1)
+            b = plan.stats()["bytes"]
+            out["results"]["%s_%s" % (pname, dname)] = {"s": round(s, 4), "GB/s": round(b / s / 1e9, 1),
+                                                        "launches": plan.stats()["n_launches"]}
+            del st
+            torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
+def workload_variational(args):
+    """Variational ansatz fused into dense 5-qubit blocks on FP32 MFMA (c64),
+    against the c128 reference (LDS passes, oracle-checked at small n)."""
+    import torch
+    import paper_2203_08826_amd as qsv
+    import workloads as W
+    n = args.n
+    circ = W.variational(n, args.layers, seed=0)
+    fused = qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_GREEDY, kmax=5, use_mfma=1)
+    fs = fused.stats()
+    a = _zero_state(n, torch.complex64)
+    qsv.qsv_plan_execute(fused, a)
+    torch.cuda.synchronize()
+    t_fused = _timed(lambda: qsv.qsv_plan_execute(fused, a), 1)
+    a = _zero_state(n, torch.complex64)
+    qsv.qsv_plan_execute(fused, a)
+    ref_plan = qsv.qsv_plan_create(n, qsv.QSV_C128, circ, mode=qsv.PLAN_PASSES)
+    b = _zero_state(n, torch.complex128)
+    t0 = time.perf_counter()
+    qsv.qsv_plan_execute(ref_plan, b)
+    torch.cuda.synchronize()
+    t_ref = time.perf_counter() - t0
+    infid = _infidelity(qsv, b, a)
+    print(json.dumps({"metric": "circuit s, TFLOP/s, infidelity vs c128", "config": {
+        "workload": "variational n=%d layers=%d (%d gates), greedy kmax=5 on FP32 MFMA" % (n, args.layers, len(circ))},
+        "fused_c64_s": round(t_fused, 4), "blocks": fs["n_blocks"], "mfma_blocks": fs["n_mfma_blocks"],
+        "launches": fs["n_launches"], "GB/s": round(fs["bytes"] / t_fused / 1e9, 1),
+        "TFLOP/s": round(fs["flops"] / t_fused / 1e12, 2), "reference_c128_passes_s": round(t_ref, 4),
+        "infidelity_c64_vs_c128": infid}), flush=True)
+
+
+def workload_adjoint(args):
+    """Adjoint-method gradient of <H> (24-qubit hardware-efficient ansatz)."""
+    import numpy as np
+    import torch
+    import paper_2203_08826_amd as qsv
+    import workloads as W
+    from paper_2203_08826_amd.autograd import expval
+    n = args.n
+    circ = W.variational(n, args.layers, seed=0)
+    theta = torch.tensor([g["params"][0] for g in circ if g["name"] in ("RY", "RZ")], dtype=torch.float64,
+                         device="cuda", requires_grad=True)
+
+    def fwd_bwd(dt):
+        th = theta.detach().clone().requires_grad_(True)
+        e = expval(th, circ, n, dtype=dt)
+        e.backward()
+        return float(e), th.grad.detach().cpu().numpy()
+
+    fwd_bwd(qsv.QSV_C64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e64, g64 = fwd_bwd(qsv.QSV_C64)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    e128, g128 = fwd_bwd(qsv.QSV_C128)
+    # parameter shift on a seeded subset, with complex128 forward runs on the GPU
+    from paper_2203_08826_amd.autograd import bind
+    rng = np.random.default_rng(0)
+    sub = sorted(rng.choice(theta.numel(), size=4, replace=False).tolist())
+    ps = []
+    for p in sub:
+        vals = []
+        for sh in (np.pi / 2, -np.pi / 2):
+            th = theta.detach().clone()
+            th[p] += sh
+            vals.append(float(expval(th, circ, n, dtype=qsv.QSV_C128)))
+        ps.append(0.5 * (vals[0] - vals[1]))
+    print(json.dumps({"metric": "forward+backward s, gradient error", "config": {
+        "workload": "hardware-efficient ansatz n=%d layers=%d, %d params, H = sum ZZ + 0.5 sum X" % (
+            n, args.layers, theta.numel())},
+        "fwd_bwd_c64_s": round(t, 4), "energy_c64": e64, "energy_c128": e128,
+        "max_abs_grad_diff_c64_vs_c128": float(np.max(np.abs(g64 - g128))),
+        "param_shift_subset": sub, "max_abs_c128_adjoint_vs_param_shift": float(np.max(np.abs(g128[sub] - np.array(ps))))}),
+        flush=True)
+
+
+def workload_learned(args):
+    """Learned plan choice vs greedy fusion vs unfused, complex64."""
+    import torch
+    import paper_2203_08826_amd as qsv
+    import workloads as W
+    from paper_2203_08826_amd import cost_model
+    loaded = os.path.exists(args.model)
+    if loaded:
+        cost_model.load_into_library(args.model)
+    n = args.n
+    res = {}
+    for name, circ in (("qft", W.qft(n)), ("supremacy_d30", W.supremacy(n, 30, seed=1))):
+        row = {}
+        states = {}
+        for pname, kw in (("learned", dict(mode=qsv.PLAN_LEARNED, kmax=2)), ("greedy2", dict(mode=qsv.PLAN_GREEDY, kmax=2)),
+                          ("unfused", dict(mode=qsv.PLAN_PER_GATE))):
+            plan = qsv.qsv_plan_create(n, qsv.QSV_C64, circ, **kw)
+            st = _zero_state(n, torch.complex64)
+            if name == "qft":
+                st[0] = 0
+                st[W.basis_index(n, 0)] = 1
+            s = _timed(lambda: qsv.qsv_plan_execute(plan, st), 0)
+            ps = plan.stats()
+            row[pname] = {"s": round(s, 4), "mode_used": ps["mode_used"], "predicted_s": ps["predicted_s"]}
+            if pname in ("learned", "unfused"):
+                states[pname] = st
+            else:
+                del st
+            torch.cuda.empty_cache()
+        row["infidelity_learned_vs_unfused"] = _infidelity(qsv, states["unfused"], states["learned"])
+        row["max_abs_diff"] = float(torch.max(torch.abs(states["unfused"] - states["learned"])).item())
+        del states
+        torch.cuda.empty_cache()
+        res[name] = row
+    print(json.dumps({"metric": "measured s: learned vs greedy vs unfused", "config": {
+        "workload": "QFT and supremacy-like depth 30 at n=%d, complex64" % n, "model_loaded": loaded}, "results": res}),
+        flush=True)
 
 
 def copy_calibration(n, steps):
@@ -75,6 +245,10 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(args.n, args.steps)
+        return
+    if args.workload != "qft":
+        {"supremacy": workload_supremacy, "variational": workload_variational, "adjoint": workload_adjoint,
+         "learned": workload_learned}[args.workload](args)
         return
 
     dev = torch.device("cuda:0")
