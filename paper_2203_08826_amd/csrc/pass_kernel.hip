@@ -32,6 +32,21 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Sum over the 64 lanes of a wave, modulo 2^64 (fixed-point turns wrap), in
+// every lane: the 32-bit halves are reduced separately (no overflow for 64
+// terms) and recombined.
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+    uint64_t lo = (uint32_t)x, hi = x >> 32;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo += (uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)lo, off, 64) |
+              ((uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)(lo >> 32), off, 64) << 32);
+        hi += (uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)hi, off, 64) |
+              ((uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)(hi >> 32), off, 64) << 32);
+    }
+    return lo + (hi << 32);
+}
+
 __device__ __forceinline__ uint32_t lds_swizzle(uint32_t l) {
     return l ^ (((l >> 4) ^ (l >> 8) ^ (l >> 12)) & 15u);
 }
@@ -198,14 +213,19 @@ __device__ __forceinline__ void phase_table(C *f, const PassOpDev &op, const Pas
                                             uint32_t t, uint64_t base) {
     constexpr int NQ = RB * (RB - 1) / 2;
     auto sum_group = [&](int g) -> uint64_t {
-        // chunk-only terms first: every operand is wave-uniform (scalar unit)
-        // (unrolled so that several term loads are in flight at once)
+        // chunk-only terms first: the same sum for every lane, so the lanes
+        // load 64 terms at a time and the wave adds them up
         uint64_t su = 0;
         const int u = op.grpu[g];
-#pragma unroll 4
-        for (int k = op.grp[g]; k < u; ++k) {
-            const PassTermDev tm = terms[k];
-            su += ((base & tm.mn) == tm.mn) ? tm.theta : 0ull;
+        const int lane = (int)(t & 63);
+        for (int k0 = op.grp[g]; k0 < u; k0 += 64) {
+            const int k = k0 + lane;
+            uint64_t th = 0;
+            if (k < u) {
+                const PassTermDev tm = terms[k];
+                th = ((base & tm.mn) == tm.mn) ? tm.theta : 0ull;
+            }
+            su += wave_sum_u64(th);
         }
         uint64_t s = 0;
         const int e = op.grp[g + 1];
