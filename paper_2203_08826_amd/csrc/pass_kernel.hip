@@ -258,6 +258,19 @@ __device__ __forceinline__ void phase_table(C *f, const PassOpDev &op, const Pas
         Q[q].x = pool[op.qf + 2 * q];
         Q[q].y = pool[op.qf + 2 * q + 1];
     }
+    if (op.noquad) {
+        // every Q is 1: f[rest | 2^top] = f[rest] * E[top]
+#pragma unroll
+        for (int top = 0; top < RB; ++top) {
+            if (top == SKIP) continue;
+#pragma unroll
+            for (int rest = 0; rest < (1 << top); ++rest) {
+                if (SKIP >= 0 && ((rest >> SKIP) & 1)) continue;
+                f[rest | (1 << top)] = cmul(f[rest], E[top]);
+            }
+        }
+        return;
+    }
     // f[rest | 2^top] = f[rest] * E[top] * prod_{i in rest} Q[top, i]
 #pragma unroll
     for (int top = 0; top < RB; ++top) {
@@ -310,10 +323,16 @@ __device__ __forceinline__ void phase_op(C *v, const PassOpDev &op, const PassTe
     for (int j = 0; j < NR; ++j) v[j] = cmul(v[j], f[j]);
 }
 
+// Prefetch when two register tiles fit the budget of 2+ waves per SIMD.
+template <typename R, int RB> struct PassPrefetch {
+    static constexpr bool value = sizeof(R) == 4 ? RB <= 4 : RB <= 3;
+};
+
 template <typename R, int RB>
 __global__ void __launch_bounds__(PT) k_pass(typename cplx_of<R>::type *__restrict__ psi, const uint8_t *__restrict__ prog,
                                              uint64_t nchunks) {
     typedef typename cplx_of<R>::type C;
+    constexpr bool PF = PassPrefetch<R, RB>::value;
     constexpr int NR = 1 << RB;
     constexpr int L = RB + PASS_THREAD_BITS;
     __shared__ C lds[1 << L];
@@ -355,17 +374,25 @@ __global__ void __launch_bounds__(PT) k_pass(typename cplx_of<R>::type *__restri
             dst[j] = psi[g];
         }
     };
-    // Software pipeline: the next chunk's loads are issued before the
+    // Software pipeline (PF): the next chunk's loads are issued before the
     // current chunk is computed, and the barriers below order LDS traffic
-    // only, so those loads stay in flight across them.
+    // only, so those loads stay in flight across them.  Without PF (register
+    // budget too small for two tiles) each chunk is loaded when its turn comes.
     uint64_t c = blockIdx.x;
     C v[NR];
-    if (c < nchunks) load_chunk(v, chunk_base(c));
+    if constexpr (PF) {
+        if (c < nchunks) load_chunk(v, chunk_base(c));
+    }
     for (; c < nchunks; c += gridDim.x) {
         const uint64_t base = chunk_base(c);
         const uint64_t cn = c + gridDim.x;
-        C vn[NR];
-        if (cn < nchunks) load_chunk(vn, chunk_base(cn));
+        C vn[PF ? NR : 1];
+        if constexpr (PF) {
+            if (cn < nchunks) load_chunk(vn, chunk_base(cn));
+        } else {
+            (void)cn;
+            load_chunk(v, base);
+        }
         int cur = H->load_part;
         for (int o = 0; o < nops; ++o) {
             const PassOpDev &op = ops[o];
@@ -433,8 +460,10 @@ __global__ void __launch_bounds__(PT) k_pass(typename cplx_of<R>::type *__restri
                 psi[g] = v[j];
             }
         }
+        if constexpr (PF) {
 #pragma unroll
-        for (int j = 0; j < NR; ++j) v[j] = vn[j];
+            for (int j = 0; j < NR; ++j) v[j] = vn[j];
+        }
     }
 }
 
@@ -489,6 +518,7 @@ static void launch_k_pass(void *state, const uint8_t *dprog, uint64_t nchunks, h
         resident[dev] = per_cu;
     }
     uint64_t g = (uint64_t)resident[dev] * device_sm_count();
+    if (!PassPrefetch<R, RB>::value) g = std::min<uint64_t>(nchunks, 1ull << 20);   // one chunk per workgroup
     if (g > nchunks) g = nchunks;
     hipLaunchKernelGGL((k_pass<R, RB>), dim3((unsigned)g), dim3(PT), 0, s, (typename cplx_of<R>::type *)state, dprog,
                        nchunks);

@@ -312,6 +312,9 @@ int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> 
             k = (int)prog.terms.size();
         }
         d.grp[ngroups] = k;
+        d.noquad = 1;
+        for (int q = 0; q < NQ; ++q)
+            if (qconst[q] != 0) d.noquad = 0;
         d.qf = (int)prog.pool.size();
         for (int q = 0; q < NQ; ++q) {
             const double ang = 2.0 * M_PI * ((double)(int64_t)qconst[q] * 5.421010862427522e-20);

@@ -52,6 +52,7 @@ struct PassOpDev {
     int32_t qf;            // pool offset of the constant pair factors (complex, one per pair)
     int32_t lf;            // pool offset of the constant single-bit factors (complex, one per register bit)
     int32_t pre;           // G1/G1R: apply the grouped phase to the |1> member first
+    int32_t noquad;        // every pair factor is exactly 1 (simpler product table)
 };
 
 // Phase term: contributes theta (fixed-point turns, 2^64 = one turn) when
