@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=30)
-    ap.add_argument("--plan", default="passes", choices=["per_gate", "greedy", "passes", "learned"])
+    ap.add_argument("--plan", default="learned", choices=["per_gate", "greedy", "passes", "learned"])
     ap.add_argument("--kmax", type=int, default=2)
     ap.add_argument("--no-baselines", action="store_true", help="skip the per-gate / c128 comparison plans")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
