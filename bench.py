@@ -212,6 +212,29 @@ def workload_learned(args):
         flush=True)
 
 
+def measured_traffic(kind):
+    """HBM bytes per launch of the dominant kernel from the committed
+    FETCH_SIZE / WRITE_SIZE summary (scaled by the copy-kernel calibration),
+    or None when that summary was taken on a different version of the kernel."""
+    if kind != "lds_pass":
+        return None
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "lds_pass_qft30_c64_traffic.md")
+    if not os.path.exists(path):
+        return None
+    info = None
+    for line in open(path):
+        if line.startswith("traffic_json:"):
+            info = json.loads(line.split(":", 1)[1])
+    if info is None:
+        return None
+    src = os.path.join(ROOT, info["source"])
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if sha != info["source_sha256_16"]:
+        return None
+    return info["bytes_per_launch"]
+
+
 def copy_calibration(n, steps):
     """Device-to-device copy of a 2^n complex64 array: the measured HBM
     ceiling, and the reference kernel for scaling FETCH_SIZE / WRITE_SIZE."""
@@ -330,7 +353,7 @@ def main():
     bytes_per_launch = d["bytes"] / d["count"]
     achieved = bytes_per_launch / avg_dur / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kind_names[dom]),
                 "kernel": kind_names[dom], "launches": d["count"], "avg_launch_ms": round(avg_dur * 1e3, 4),
                 "bytes_per_launch": bytes_per_launch}
 
