@@ -194,7 +194,7 @@ def workload_learned(args):
             if name == "qft":
                 st[0] = 0
                 st[W.basis_index(n, 0)] = 1
-            s = _timed(lambda: qsv.qsv_plan_execute(plan, st), 0)
+            s = _timed(lambda: qsv.qsv_plan_execute(plan, st), 1)
             ps = plan.stats()
             row[pname] = {"s": round(s, 4), "mode_used": ps["mode_used"], "predicted_s": ps["predicted_s"]}
             if pname in ("learned", "unfused"):
