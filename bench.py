@@ -65,9 +65,12 @@ def _zero_state(n, dtype):
 
 
 def _infidelity(qsv, a, b):
+    """1 - |<a|b>|^2 / (<a|a><b|b>), float64 sums (the states are widened only
+    when their dtypes differ)."""
     import torch
-    a = a.to(torch.complex128)
-    b = b.to(torch.complex128)
+    if a.dtype != b.dtype:
+        a = a.to(torch.complex128)
+        b = b.to(torch.complex128)
     ov = qsv.qsv_inner(a, b).cpu().numpy()
     na = qsv.qsv_norm2(a).cpu().numpy()[0]
     nb = qsv.qsv_norm2(b).cpu().numpy()[0]
