@@ -21,11 +21,16 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
 # Packed FP32 instructions are switched off for all device code.
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
+# Per-file extras.  The pass kernel keeps a register tile of 2^RB amplitudes
+# indexed by compile-time constants; SimplifyCFG's sinking of the common
+# stores of switch cases would turn those into a phi of tile addresses and
+# leave the tile in scratch memory, so that transform is off for this file.
+EXTRA = {"pass_kernel.hip": ["-mllvm", "-simplifycfg-sink-common=false"]}
 
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + COMMON + DEVICE
+    cmd = [HIPCC] + COMMON + DEVICE + EXTRA.get(os.path.basename(src), [])
     if src.endswith(".hip"):
         cmd += ["-x", "hip"]
     cmd += ["-c", src, "-o", obj]

@@ -60,40 +60,45 @@ __device__ __forceinline__ C cmadd(C a, C g, C b, C h) {
     return r;
 }
 
+// Controls: a thread whose thread/chunk control bits are not all set applies
+// the identity (matrix chosen once per op); register-bit controls (cj) are
+// the same for every lane, so pairs they exclude are skipped by a uniform
+// branch.  Uncontrolled gates cost only the FMAs.
 template <typename C, typename R, int NR, int I>
 __device__ __forceinline__ void g1(C *v, const R *m, uint32_t cj, bool tok) {
     C g00, g01, g10, g11;
-    g00.x = m[0]; g00.y = m[1]; g01.x = m[2]; g01.y = m[3];
-    g10.x = m[4]; g10.y = m[5]; g11.x = m[6]; g11.y = m[7];
+    g00.x = tok ? m[0] : (R)1; g00.y = tok ? m[1] : (R)0;
+    g01.x = tok ? m[2] : (R)0; g01.y = tok ? m[3] : (R)0;
+    g10.x = tok ? m[4] : (R)0; g10.y = tok ? m[5] : (R)0;
+    g11.x = tok ? m[6] : (R)1; g11.y = tok ? m[7] : (R)0;
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if ((j >> I) & 1) continue;
+        if (((uint32_t)j & cj) != cj) continue;
         const int j1 = j | (1 << I);
-        const bool ok = tok && (((uint32_t)j & cj) == cj);
         const C a = v[j], b = v[j1];
-        const C o0 = cmadd(a, g00, b, g01);
-        const C o1 = cmadd(a, g10, b, g11);
-        v[j] = ok ? o0 : a;
-        v[j1] = ok ? o1 : b;
+        v[j] = cmadd(a, g00, b, g01);
+        v[j1] = cmadd(a, g10, b, g11);
     }
 }
 
 template <typename C, typename R, int NR, int I>
 __device__ __forceinline__ void g1r(C *v, const R *m, uint32_t cj, bool tok) {
-    const R g00 = m[0], g01 = m[1], g10 = m[2], g11 = m[3];
+    const R g00 = tok ? m[0] : (R)1, g01 = tok ? m[1] : (R)0;
+    const R g10 = tok ? m[2] : (R)0, g11 = tok ? m[3] : (R)1;
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if ((j >> I) & 1) continue;
+        if (((uint32_t)j & cj) != cj) continue;
         const int j1 = j | (1 << I);
-        const bool ok = tok && (((uint32_t)j & cj) == cj);
         const C a = v[j], b = v[j1];
         C o0, o1;
         o0.x = g00 * a.x + g01 * b.x;
         o0.y = g00 * a.y + g01 * b.y;
         o1.x = g10 * a.x + g11 * b.x;
         o1.y = g10 * a.y + g11 * b.y;
-        v[j] = ok ? o0 : a;
-        v[j1] = ok ? o1 : b;
+        v[j] = o0;
+        v[j1] = o1;
     }
 }
 
@@ -102,14 +107,15 @@ __device__ __forceinline__ void g2(C *v, const R *m, uint32_t cj, bool tok) {
     C g[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-        g[e].x = m[2 * e];
-        g[e].y = m[2 * e + 1];
+        const R one = (e % 5 == 0) ? (R)1 : (R)0;   // identity for threads whose controls are not set
+        g[e].x = tok ? m[2 * e] : one;
+        g[e].y = tok ? m[2 * e + 1] : (R)0;
     }
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if (((j >> I1) & 1) || ((j >> I2) & 1)) continue;
+        if (((uint32_t)j & cj) != cj) continue;
         const int jj[4] = {j, j | (1 << I2), j | (1 << I1), j | (1 << I1) | (1 << I2)};
-        const bool ok = tok && (((uint32_t)j & cj) == cj);
         C a[4], o[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) a[r] = v[jj[r]];
@@ -122,13 +128,19 @@ __device__ __forceinline__ void g2(C *v, const R *m, uint32_t cj, bool tok) {
             o[r] = acc;
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[jj[r]] = ok ? o[r] : a[r];
+        for (int r = 0; r < 4; ++r) v[jj[r]] = o[r];
     }
 }
 
+// Phase sources of a pass op, as laid out in the program.
+template <typename R> struct PhaseSrc {
+    const R *pool;
+    const PassSlotDev *slots;
+    const PassTermDev *terms;
+};
+
 template <typename C, typename R, int NR, int RB>
-__device__ void full_phase_table(C *f, const PassOpDev &op, const PassTermDev *terms, const R *pool, uint32_t t,
-                                 uint64_t base);
+__device__ void phase_factors(C *f, const PassOpDev &op, const PhaseSrc<R> &src, uint32_t t, uint64_t base, int sk);
 
 // The phase that precedes a one-qubit gate on register bit I multiplies only
 // its |1> members; its terms never need bit I, so f[j] = f[j | 2^I].
@@ -140,11 +152,11 @@ __device__ __forceinline__ void apply_pre(C *v, const C *f) {
 }
 
 template <typename C, typename R, int NR, int RB>
-__device__ __forceinline__ void dispatch_g1(const PassOpDev &op, bool real, C *v, const R *pool,
-                                            const PassTermDev *terms, uint32_t t, uint64_t base, bool tok) {
-    const R *m = pool + op.mat;
+__device__ __forceinline__ void dispatch_g1(const PassOpDev &op, bool real, C *v, const PhaseSrc<R> &src, uint32_t t,
+                                            uint64_t base, bool tok) {
+    const R *m = src.pool + op.mat;
     C f[NR];
-    if (op.pre) full_phase_table<C, R, NR, RB>(f, op, terms, pool, t, base);
+    if (op.pre) phase_factors<C, R, NR, RB>(f, op, src, t, base, op.a);
 #define QSV_G1(I)                                                               \
     case I:                                                                     \
         if constexpr (I < RB) {                                                 \
@@ -205,106 +217,101 @@ __device__ __forceinline__ double2 expi(uint64_t ph, double) {
     return r;
 }
 
-// Factor table f[j] of a grouped phase (see PassOpDev) for every register
-// index j with bit SKIP clear (SKIP = -1: every j).  Terms of the last group
-// are not included (evaluated per j by the caller).
-template <typename C, typename R, int NR, int RB, int SKIP>
-__device__ __forceinline__ void phase_table(C *f, const PassOpDev &op, const PassTermDev *terms, const R *pool,
-                                            uint32_t t, uint64_t base) {
-    constexpr int NQ = RB * (RB - 1) / 2;
-    auto sum_group = [&](int g) -> uint64_t {
-        // chunk-only terms first: the same sum for every lane, so the lanes
-        // load 64 terms at a time and the wave adds them up
-        uint64_t su = 0;
-        const int u = op.grpu[g];
-        const int lane = (int)(t & 63);
-        for (int k0 = op.grp[g]; k0 < u; k0 += 64) {
-            const int k = k0 + lane;
-            uint64_t th = 0;
-            if (k < u) {
-                const PassTermDev tm = terms[k];
-                th = ((base & tm.mn) == tm.mn) ? tm.theta : 0ull;
-            }
-            su += wave_sum_u64(th);
-        }
-        uint64_t s = 0;
-        const int e = op.grp[g + 1];
-#pragma unroll 4
-        for (int k = u; k < e; ++k) {
-            const PassTermDev tm = terms[k];
-            const bool ok = ((t & tm.mt) == tm.mt) && ((base & tm.mn) == tm.mn);
-            s += ok ? tm.theta : 0ull;
-        }
-        return su + s;
-    };
+__device__ __forceinline__ float2 readlane(float2 v, int l) {
+    float2 r;
+    r.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), l));
+    r.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), l));
+    return r;
+}
+__device__ __forceinline__ double readlane(double v, int l) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ double2 readlane(double2 v, int l) {
+    double2 r;
+    r.x = readlane(v.x, l);
+    r.y = readlane(v.y, l);
+    return r;
+}
+
+// Factor table f[j] of an op's phase (see PassOpDev) for the register
+// indices j with bit sk clear (sk = -1: every j).  One copy of this code
+// serves every PHASE op and every pre-phased one-qubit gate; the branches on
+// op fields are uniform.
+template <typename C, typename R, int NR, int RB>
+__device__ void phase_factors(C *f, const PassOpDev &op, const PhaseSrc<R> &src, uint32_t t, uint64_t base, int sk) {
     C one;
     one.x = 1;
     one.y = 0;
-    f[0] = (op.grp[1] > op.grp[0]) ? expi(sum_group(0), R()) : one;
-    // single-bit factors: a host constant times the per-thread part (if any)
-    C E[RB];
+    C F[RB + 1];
 #pragma unroll
-    for (int i = 0; i < RB; ++i) {
-        if (i == SKIP) continue;
-        C e;
-        e.x = pool[op.lf + 2 * i];
-        e.y = pool[op.lf + 2 * i + 1];
-        if (op.grp[2 + i] > op.grp[1 + i]) e = cmul(e, expi(sum_group(1 + i), R()));
-        E[i] = e;
+    for (int g = 0; g <= RB; ++g) {
+        F[g] = one;
+        if (op.tab[g] >= 0) {
+            F[g].x = src.pool[op.tab[g] + 2 * t];
+            F[g].y = src.pool[op.tab[g] + 2 * t + 1];
+        }
     }
-    C Q[NQ > 0 ? NQ : 1];
+    // chunk-dependent slots: lane s sums slot s, one sincos for the wave,
+    // then every thread multiplies in the slots its index covers
+    const int s0 = op.sl[0], s1 = op.sl[RB + 1];
+    if (s1 > s0) {
+        const int lane = (int)(t & 63);
+        uint64_t ph = 0;
+        if (lane < s1 - s0) {
+            const PassSlotDev S = src.slots[s0 + lane];
+            for (int k = S.begin; k < S.end; ++k) {
+                const PassTermDev tm = src.terms[k];
+                ph += ((base & tm.mn) == tm.mn) ? tm.theta : 0ull;
+            }
+        }
+        const C e = expi(ph, R());
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        Q[q].x = pool[op.qf + 2 * q];
-        Q[q].y = pool[op.qf + 2 * q + 1];
+        for (int g = 0; g <= RB; ++g) {
+            for (int s = op.sl[g]; s < op.sl[g + 1]; ++s) {
+                const C es = readlane(e, s - s0);
+                const uint32_t mt = src.slots[s].mt;
+                if ((t & mt) == mt) F[g] = cmul(F[g], es);
+            }
+        }
     }
-    if (op.noquad) {
-        // every Q is 1: f[rest | 2^top] = f[rest] * E[top]
+    // f[j] = Fc[j] * F_0 * prod_{i in j} F_{1+i}
+    if (op.var & 2) {
+        f[0] = F[0];
 #pragma unroll
         for (int top = 0; top < RB; ++top) {
-            if (top == SKIP) continue;
+            if (top == sk) continue;
 #pragma unroll
             for (int rest = 0; rest < (1 << top); ++rest) {
-                if (SKIP >= 0 && ((rest >> SKIP) & 1)) continue;
-                f[rest | (1 << top)] = cmul(f[rest], E[top]);
+                if (sk >= 0 && ((rest >> sk) & 1)) continue;
+                f[rest | (1 << top)] = cmul(f[rest], F[1 + top]);
             }
         }
-        return;
-    }
-    // f[rest | 2^top] = f[rest] * E[top] * prod_{i in rest} Q[top, i]
+    } else {
 #pragma unroll
-    for (int top = 0; top < RB; ++top) {
-        if (top == SKIP) continue;
-        C Rt[1 << (RB - 1)];
-#pragma unroll
-        for (int rest = 0; rest < (1 << top); ++rest) {
-            if (SKIP >= 0 && ((rest >> SKIP) & 1)) continue;
-            if (rest == 0) {
-                Rt[0] = E[top];
-            } else {
-                const int hb = 31 - __builtin_clz(rest);
-                Rt[rest] = cmul(Rt[rest ^ (1 << hb)], Q[top * (top - 1) / 2 + hb]);
-            }
-            f[rest | (1 << top)] = cmul(f[rest], Rt[rest]);
-        }
+        for (int j = 0; j < NR; ++j) f[j] = F[0];
     }
-}
-
-// Complete factor table of a grouped phase, including the terms of the last
-// group (evaluated per register index).  One copy of this code serves every
-// PHASE op and every pre-phased one-qubit gate.
-template <typename C, typename R, int NR, int RB>
-__device__ void full_phase_table(C *f, const PassOpDev &op, const PassTermDev *terms, const R *pool, uint32_t t,
-                                 uint64_t base) {
-    constexpr int NQ = RB * (RB - 1) / 2;
-    phase_table<C, R, NR, RB, -1>(f, op, terms, pool, t, base);
-    const int gen_b = op.grp[1 + RB + NQ], gen_e = op.grp[2 + RB + NQ];
-    if (gen_e > gen_b) {
+    if (op.fc >= 0) {
+        const R *fc = src.pool + op.fc;
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
+            if (sk >= 0 && ((j >> sk) & 1)) continue;
+            C c;
+            c.x = fc[2 * j];
+            c.y = fc[2 * j + 1];
+            f[j] = op.var ? cmul(f[j], c) : c;
+        }
+    }
+    // general terms: evaluated per register index
+    if (op.gen_e > op.gen_b) {
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            if (sk >= 0 && ((j >> sk) & 1)) continue;
             uint64_t ph = 0;
-            for (int k = gen_b; k < gen_e; ++k) {
-                const PassTermDev tm = terms[k];
+            for (int k = op.gen_b; k < op.gen_e; ++k) {
+                const PassTermDev tm = src.terms[k];
                 const bool ok =
                     ((t & tm.mt) == tm.mt) && ((base & tm.mn) == tm.mn) && (((uint32_t)j & tm.mj) == tm.mj);
                 ph += ok ? tm.theta : 0ull;
@@ -315,10 +322,10 @@ __device__ void full_phase_table(C *f, const PassOpDev &op, const PassTermDev *t
 }
 
 template <typename C, typename R, int NR, int RB>
-__device__ __forceinline__ void phase_op(C *v, const PassOpDev &op, const PassTermDev *terms, const R *pool,
-                                         uint32_t t, uint64_t base) {
+__device__ __forceinline__ void phase_op(C *v, const PassOpDev &op, const PhaseSrc<R> &src, uint32_t t,
+                                         uint64_t base) {
     C f[NR];
-    full_phase_table<C, R, NR, RB>(f, op, terms, pool, t, base);
+    phase_factors<C, R, NR, RB>(f, op, src, t, base, -1);
 #pragma unroll
     for (int j = 0; j < NR; ++j) v[j] = cmul(v[j], f[j]);
 }
@@ -340,8 +347,11 @@ __global__ void __launch_bounds__(PT) k_pass(typename cplx_of<R>::type *__restri
     const PassHeaderDev *H = (const PassHeaderDev *)prog;
     const PassPartition *parts = (const PassPartition *)(prog + H->off_part);
     const PassOpDev *ops = (const PassOpDev *)(prog + H->off_ops);
-    const R *pool = (const R *)(prog + H->off_pool);
-    const PassTermDev *terms = (const PassTermDev *)(prog + H->off_terms);
+    PhaseSrc<R> src;
+    src.pool = (const R *)(prog + H->off_pool);
+    src.slots = (const PassSlotDev *)(prog + H->off_slots);
+    src.terms = (const PassTermDev *)(prog + H->off_terms);
+    const R *pool = src.pool;
     const uint32_t t = threadIdx.x;
     const int nops = H->nops;
 
@@ -398,11 +408,14 @@ __global__ void __launch_bounds__(PT) k_pass(typename cplx_of<R>::type *__restri
             const PassOpDev &op = ops[o];
             const bool tok = ((t & op.ct) == op.ct) && ((base & op.cn) == op.cn);
             switch (op.kind) {
-            case POP_G1: dispatch_g1<C, R, NR, RB>(op, false, v, pool, terms, t, base, tok); break;
-            case POP_G1R: dispatch_g1<C, R, NR, RB>(op, true, v, pool, terms, t, base, tok); break;
+            case POP_G1: dispatch_g1<C, R, NR, RB>(op, false, v, src, t, base, tok); break;
+            case POP_G1R: dispatch_g1<C, R, NR, RB>(op, true, v, src, t, base, tok); break;
             case POP_G2: dispatch_g2<C, R, NR, RB>(op.a, op.b, v, pool + op.mat, op.cj, tok); break;
-            case POP_PHASE: phase_op<C, R, NR, RB>(v, op, terms, pool, t, base); break;
+            case POP_PHASE: phase_op<C, R, NR, RB>(v, op, src, t, base); break;
             case POP_EXCHANGE: {
+                // The swizzle is linear over GF(2) and the bits of a local
+                // index are disjoint, so the swizzled slot of register index
+                // j is the thread's slot XOR the slots of j's register bits.
                 const PassPartition &P = parts[cur];
                 const PassPartition &Q = parts[op.a];
                 uint32_t lt = 0, lq = 0;
@@ -413,24 +426,24 @@ __global__ void __launch_bounds__(PT) k_pass(typename cplx_of<R>::type *__restri
                         lq |= 1u << Q.thr_l[u];
                     }
                 }
-                lds_barrier();
+                uint32_t ap[NR], aq[NR];
+                ap[0] = lds_swizzle(lt);
+                aq[0] = lds_swizzle(lq);
 #pragma unroll
-                for (int j = 0; j < NR; ++j) {
-                    uint32_t l = lt;
+                for (int i = 0; i < RB; ++i) {
+                    const uint32_t sp = lds_swizzle(1u << P.reg_l[i]), sq = lds_swizzle(1u << Q.reg_l[i]);
 #pragma unroll
-                    for (int i = 0; i < RB; ++i)
-                        if ((j >> i) & 1) l |= 1u << P.reg_l[i];
-                    lds[lds_swizzle(l)] = v[j];
+                    for (int r = 0; r < (1 << i); ++r) {
+                        ap[r | (1 << i)] = ap[r] ^ sp;
+                        aq[r | (1 << i)] = aq[r] ^ sq;
+                    }
                 }
                 lds_barrier();
 #pragma unroll
-                for (int j = 0; j < NR; ++j) {
-                    uint32_t l = lq;
+                for (int j = 0; j < NR; ++j) lds[ap[j]] = v[j];
+                lds_barrier();
 #pragma unroll
-                    for (int i = 0; i < RB; ++i)
-                        if ((j >> i) & 1) l |= 1u << Q.reg_l[i];
-                    v[j] = lds[lds_swizzle(l)];
-                }
+                for (int j = 0; j < NR; ++j) v[j] = lds[aq[j]];
                 cur = op.a;
                 break;
             }
@@ -494,12 +507,15 @@ void PassProgram::serialise() {
     off = align(off + pool.size() * sizeof(double));   // room for the widest real type
     h.off_terms = (int)off;
     off = align(off + terms.size() * sizeof(PassTermDev));
+    h.off_slots = (int)off;
+    off = align(off + slots.size() * sizeof(PassSlotDev));
     h.total_bytes = (int)off;
     blob.assign(off, 0);
     std::memcpy(blob.data(), &h, sizeof(h));
     if (!parts.empty()) std::memcpy(blob.data() + h.off_part, parts.data(), parts.size() * sizeof(PassPartition));
     if (!ops.empty()) std::memcpy(blob.data() + h.off_ops, ops.data(), ops.size() * sizeof(PassOpDev));
     if (!terms.empty()) std::memcpy(blob.data() + h.off_terms, terms.data(), terms.size() * sizeof(PassTermDev));
+    if (!slots.empty()) std::memcpy(blob.data() + h.off_slots, slots.data(), slots.size() * sizeof(PassSlotDev));
     // the pool is written per dtype at launch time (float or double)
 }
 

@@ -243,6 +243,7 @@ int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> 
     prog.ops.clear();
     prog.pool.clear();
     prog.terms.clear();
+    prog.slots.clear();
     auto reg_index = [&](const Part &p, int l) {
         for (int i = 0; i < (int)p.reg.size(); ++i)
             if (p.reg[i] == l) return i;
@@ -262,70 +263,115 @@ int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> 
         prog.ops.push_back(d);
         cur = np;
     };
-    // Group phase terms by the register bits they need under `cur` (see
-    // PassOpDev); `skip` is a local position removed from every term (the
-    // target of a pre-phased G1, implied by its |1> member).
-    const int NQ = RB * (RB - 1) / 2;
-    const int ngroups = 1 + RB + NQ + 1;
+    // Encode the phase terms of an op as PassOpDev describes, under the
+    // partition `cur`; `skip` is a local position removed from every term
+    // (the target of a pre-phased G1, implied by its |1> member).
+    const int NR = 1 << RB;
+    auto turns_to_unit = [](uint64_t th, double &re, double &im) {
+        const double ang = 2.0 * M_PI * ((double)(int64_t)th * 5.421010862427522e-20);   // 2^-64 turns
+        re = std::cos(ang);
+        im = std::sin(ang);
+    };
     auto encode_terms = [&](const std::vector<std::pair<uint64_t, std::pair<uint32_t, uint64_t>>> &terms, int skip,
                             PassOpDev &d) {
-        std::vector<std::vector<PassTermDev>> groups(ngroups);
-        std::vector<uint64_t> qconst(NQ > 0 ? NQ : 1, 0), lconst(RB, 0);
+        std::vector<uint64_t> fconst(NR, 0);
+        std::vector<std::vector<PassTermDev>> thr(RB + 1);                    // thread bits only
+        std::map<std::pair<int, uint32_t>, std::vector<PassTermDev>> chunk;  // (group, thread mask) -> terms
+        std::vector<PassTermDev> gen;
         for (auto &t : terms) {
             PassTermDev td;
             std::memset(&td, 0, sizeof(td));
             td.theta = t.first;
             td.mn = t.second.second;
-            std::vector<int> regs;
+            int nreg = 0, reg = -1;
             for (int l = 0; l < L; ++l) {
                 if (!((t.second.first >> l) & 1) || l == skip) continue;
                 const int i = reg_index(cur, l);
                 if (i >= 0) {
-                    regs.push_back(i);
                     td.mj |= 1u << i;
+                    reg = i;
+                    ++nreg;
                 } else {
                     td.mt |= 1u << thr_index(cur, l);
                 }
             }
-            int gidx;
-            if (regs.empty()) gidx = 0;
-            else if (regs.size() == 1 && td.mt == 0 && td.mn == 0) {
-                lconst[regs[0]] += td.theta;   // constant: folded into a host factor
+            if (td.mt == 0 && td.mn == 0) {
+                // register bits only: folded into the host table Fc
+                for (int j = 0; j < NR; ++j)
+                    if (((uint32_t)j & td.mj) == td.mj) fconst[j] += td.theta;
                 continue;
-            } else if (regs.size() == 1) gidx = 1 + regs[0];
-            else if (regs.size() == 2 && td.mt == 0 && td.mn == 0) {
-                const int a = std::max(regs[0], regs[1]), b = std::min(regs[0], regs[1]);
-                qconst[a * (a - 1) / 2 + b] += td.theta;   // constant: folded into a host factor
+            }
+            if (nreg >= 2) {
+                gen.push_back(td);
                 continue;
-            } else gidx = ngroups - 1;
-            groups[gidx].push_back(td);
+            }
+            const int g = nreg ? 1 + reg : 0;
+            if (td.mn == 0) thr[g].push_back(td);
+            else chunk[{g, td.mt}].push_back(td);
         }
-        int k = (int)prog.terms.size();
-        for (int g = 0; g < ngroups; ++g) {
-            d.grp[g] = k;
-            // chunk-only terms (no thread bit) first, so the device sums them on the scalar unit
-            for (auto &td : groups[g])
-                if (td.mt == 0) prog.terms.push_back(td);
-            d.grpu[g] = (int)prog.terms.size();
-            for (auto &td : groups[g])
-                if (td.mt != 0) prog.terms.push_back(td);
-            k = (int)prog.terms.size();
+        // per-thread tables (each 256 complex; bounded so a program fits a staging slot)
+        for (int g = 0; g <= PASS_MAX_RB; ++g) d.tab[g] = -1;
+        for (int g = 0; g <= RB; ++g) {
+            if (thr[g].empty()) continue;
+            if (prog.pool.size() + 512 > 16384) {
+                for (auto &td : thr[g]) chunk[{g, td.mt}].push_back(td);   // evaluated as slots instead
+                continue;
+            }
+            d.tab[g] = (int)prog.pool.size();
+            for (uint32_t tt = 0; tt < 256; ++tt) {
+                uint64_t ph = 0;
+                for (auto &td : thr[g])
+                    if ((tt & td.mt) == td.mt) ph += td.theta;
+                double re, im;
+                turns_to_unit(ph, re, im);
+                prog.pool.push_back(re);
+                prog.pool.push_back(im);
+            }
         }
-        d.grp[ngroups] = k;
-        d.noquad = 1;
-        for (int q = 0; q < NQ; ++q)
-            if (qconst[q] != 0) d.noquad = 0;
-        d.qf = (int)prog.pool.size();
-        for (int q = 0; q < NQ; ++q) {
-            const double ang = 2.0 * M_PI * ((double)(int64_t)qconst[q] * 5.421010862427522e-20);
-            prog.pool.push_back(std::cos(ang));
-            prog.pool.push_back(std::sin(ang));
+        // slots, grouped by F_g; long sums are split, and past the per-op
+        // limit the terms are evaluated as general terms
+        const int s_first = (int)prog.slots.size();
+        for (int g = 0; g <= RB; ++g) {
+            d.sl[g] = (int)prog.slots.size();
+            for (auto &kv : chunk) {
+                if (kv.first.first != g) continue;
+                const auto &ts = kv.second;
+                for (size_t b = 0; b < ts.size(); b += PASS_SLOT_TERMS) {
+                    const size_t e = std::min(ts.size(), b + PASS_SLOT_TERMS);
+                    if ((int)prog.slots.size() - s_first >= PASS_MAX_SLOTS) {
+                        for (size_t k = b; k < e; ++k) gen.push_back(ts[k]);
+                        continue;
+                    }
+                    PassSlotDev sd;
+                    std::memset(&sd, 0, sizeof(sd));
+                    sd.mt = kv.first.second;
+                    sd.begin = (int)prog.terms.size();
+                    for (size_t k = b; k < e; ++k) prog.terms.push_back(ts[k]);
+                    sd.end = (int)prog.terms.size();
+                    prog.slots.push_back(sd);
+                }
+            }
         }
-        d.lf = (int)prog.pool.size();
-        for (int i = 0; i < RB; ++i) {
-            const double ang = 2.0 * M_PI * ((double)(int64_t)lconst[i] * 5.421010862427522e-20);
-            prog.pool.push_back(std::cos(ang));
-            prog.pool.push_back(std::sin(ang));
+        for (int g = RB + 1; g <= PASS_MAX_RB + 1; ++g) d.sl[g] = (int)prog.slots.size();
+        d.gen_b = (int)prog.terms.size();
+        for (auto &td : gen) prog.terms.push_back(td);
+        d.gen_e = (int)prog.terms.size();
+        d.var = 0;
+        if (d.tab[0] >= 0 || d.sl[1] > d.sl[0]) d.var |= 1;
+        for (int g = 1; g <= RB; ++g)
+            if (d.tab[g] >= 0 || d.sl[g + 1] > d.sl[g]) d.var |= 2;
+        d.fc = -1;
+        bool any = false;
+        for (int j = 0; j < NR; ++j)
+            if (fconst[j] != 0) any = true;
+        if (any) {
+            d.fc = (int)prog.pool.size();
+            for (int j = 0; j < NR; ++j) {
+                double re, im;
+                turns_to_unit(fconst[j], re, im);
+                prog.pool.push_back(re);
+                prog.pool.push_back(im);
+            }
         }
     };
     for (size_t o = 0; o < ops.size(); ++o) {

@@ -22,7 +22,8 @@ namespace qsv {
 constexpr int PASS_THREAD_BITS = 8;
 constexpr int PASS_MAX_RB = 5;
 constexpr int PASS_MAX_L = PASS_MAX_RB + PASS_THREAD_BITS;
-constexpr int PASS_GROUPS = 1 + PASS_MAX_RB + PASS_MAX_RB * (PASS_MAX_RB - 1) / 2 + 1;   // c0, lin, quad, general
+constexpr int PASS_MAX_SLOTS = 64;       // per op: one per lane of a wave
+constexpr int PASS_SLOT_TERMS = 32;      // longer slots are split
 
 enum PassOpKind : int32_t { POP_EXCHANGE = 1, POP_G1 = 2, POP_G1R = 3, POP_G2 = 4, POP_PHASE = 5 };
 
@@ -32,14 +33,18 @@ struct PassPartition {
 };
 
 // Phase evaluation (PHASE ops, and the phase a G1/G1R op applies to its
-// |1> member first when `pre` is set): terms are grouped by the register
-// bits they need under the op's partition --
-//   group 0        : no register bit      -> per-thread sum A0
-//   group 1 + i    : register bit i only  -> per-thread sum A_i
-//   group 1+RB+q   : register pair q      -> constant, host factor in the pool at qf
-//   last group     : everything else      -> evaluated per register index
-// and the factor of register index j is e^{iA0} prod_{i in j} e^{iA_i}
-// prod_{pairs in j} Q_pair, built as a product table.
+// |1> member first when `pre` is set).  The phase of register index j in
+// thread t of the chunk with base index `base` factors as
+//   f[j] = Fc[j] * F_0 * prod_{i in j} F_{1+i}
+// where Fc is a host table of the terms that need register bits only, and
+// F_g (g = 0: no register bit, g = 1+i: register bit i and no other) is the
+// product of
+//   - a host table over the 256 threads (terms that need thread bits only),
+//   - "slots": sums of terms that need chunk bits, one per thread mask; the
+//     64 lanes of a wave evaluate up to 64 slots side by side, and every
+//     thread whose bits cover a slot's mask multiplies in its factor.
+// Terms that need two or more register bits together with thread or chunk
+// bits ("general" terms) are evaluated per register index.
 struct PassOpDev {
     int32_t kind;
     int32_t a, b;          // G1: register bit a.  G2: register bits a > b.  EXCHANGE: partition index
@@ -47,22 +52,31 @@ struct PassOpDev {
     uint32_t cj;           // controls on register bits (mask over j)
     int32_t mat;           // offset into the real pool
     uint64_t cn;           // controls on non-local bits (mask over global index)
-    int32_t grp[PASS_GROUPS + 1];   // term ranges [grp[g], grp[g+1]) per group
-    int32_t grpu[PASS_GROUPS];      // terms [grp[g], grpu[g]) need no thread bit (uniform per chunk)
-    int32_t qf;            // pool offset of the constant pair factors (complex, one per pair)
-    int32_t lf;            // pool offset of the constant single-bit factors (complex, one per register bit)
-    int32_t pre;           // G1/G1R: apply the grouped phase to the |1> member first
-    int32_t noquad;        // every pair factor is exactly 1 (simpler product table)
+    int32_t tab[PASS_MAX_RB + 1];   // pool offset of the per-thread table of F_g (256 complex), or -1
+    int32_t sl[PASS_MAX_RB + 2];    // slots [sl[g], sl[g+1]) belong to F_g
+    int32_t gen_b, gen_e;           // general terms
+    int32_t fc;            // pool offset of Fc (2^RB complex), or -1 when every entry is 1
+    int32_t var;           // bit 0: F_0 is not 1; bit 1: some F_{1+i} is not 1
+    int32_t pre;           // G1/G1R: apply the phase to the |1> member first
+    int32_t pad;
 };
 
 // Phase term: contributes theta (fixed-point turns, 2^64 = one turn) when
-// every bit of mt (thread index), of mn (global chunk base) and of the
-// group's register bits is 1.  General-group terms also carry mj.
+// every bit of mn (global chunk base) is 1 -- and, for general terms, every
+// bit of mt (thread index) and of mj (register index).
 struct PassTermDev {
     uint64_t mn;
     uint64_t theta;
     uint32_t mt;
     uint32_t mj;
+};
+
+// A slot: the chunk-dependent phase sum of terms [begin, end), applied in
+// the threads whose index covers mt.
+struct PassSlotDev {
+    int32_t begin, end;
+    uint32_t mt;
+    int32_t pad;
 };
 
 struct PassHeaderDev {
@@ -73,7 +87,7 @@ struct PassHeaderDev {
     int32_t in_pos[PASS_MAX_L];    // global bit of local position l (load)
     int32_t out_pos[PASS_MAX_L];   // global bit of local position l (store)
     uint64_t lowmask[PASS_MAX_L];  // sorted local bits, for the chunk base
-    int32_t off_part, off_ops, off_pool, off_terms;   // byte offsets from the header
+    int32_t off_part, off_ops, off_pool, off_terms, off_slots;   // byte offsets from the header
     int32_t total_bytes;
     int32_t relabel;               // 1: some thread stores where another loaded
 };
@@ -89,6 +103,7 @@ struct PassProgram {
     std::vector<PassOpDev> ops;
     std::vector<double> pool;
     std::vector<PassTermDev> terms;
+    std::vector<PassSlotDev> slots;
     int n_gates = 0;                      // circuit gates folded into this pass
     std::vector<uint8_t> blob;            // serialised program
     void serialise();
