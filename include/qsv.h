@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define QSV_ABI_VERSION 1
+#define QSV_ABI_VERSION 2
 
 /* Status codes. */
 enum {
@@ -160,6 +160,11 @@ typedef struct qsv_plan_options {
     int kmax;          /* fusion width for QSV_PLAN_GREEDY, 1..6 (default 2) */
     int local_bits;    /* chunk bits for QSV_PLAN_PASSES, 0 = library default */
     int use_mfma;      /* 1: fused complex64 blocks of 4..6 qubits use MFMA */
+    int jit;           /* 1: every LDS pass of the plan is compiled (hiprtc, at
+                        * qsv_plan_create) into a kernel specialised for its
+                        * gates -- constants, bit assignments and op sequence
+                        * fixed at compile time; results equal the interpreted
+                        * pass kernel's up to rounding order.  0: interpreted. */
 } qsv_plan_options;
 
 typedef struct qsv_plan qsv_plan;
@@ -172,14 +177,18 @@ typedef struct qsv_plan_stats {
     int n_mfma_blocks;     /* of which on MFMA */
     int n_passes;          /* LDS passes */
     int mode_used;         /* QSV_PLAN_* finally used (LEARNED resolves to another) */
+    int n_jit_passes;      /* LDS passes running as compiled kernels */
     double bytes;          /* algorithmic HBM bytes per execution */
     double flops;          /* algorithmic flops per execution */
     double predicted_s;    /* cost-model prediction, 0 if none */
 } qsv_plan_stats;
 
 /* Build a plan on the host (no HIP call unless mode = LEARNED with a model,
- * which runs the MLP inference kernel on the current device).  The gates are
- * copied; the caller may free them afterwards. */
+ * which runs the MLP inference kernel on the current device).  With
+ * opts->jit the passes are compiled here (host compiler only; each kernel is
+ * loaded on a device at its first execution there); a compilation failure
+ * returns QSV_ERR_UNSUPPORTED with the compiler log in qsv_last_error.  The
+ * gates are copied; the caller may free them afterwards. */
 int qsv_plan_create(int n, int dtype, const qsv_gate *gates, int ngates,
                     const qsv_plan_options *opts, qsv_plan **out);
 int qsv_plan_stats_get(const qsv_plan *plan, qsv_plan_stats *out);
@@ -194,9 +203,13 @@ int qsv_plan_execute_ops(const qsv_plan *plan, void *state, int first, int count
  * bytes and flops of op `index`; any output pointer may be NULL. */
 int qsv_plan_op_info(const qsv_plan *plan, int index, int *kind, double *bytes, double *flops);
 /* Host-only: copy the serialised program of LDS-pass op `index` (layout in
- * plan_internal.h: header, partitions, ops, real pool, phase terms; the pool
+ * plan_internal.h: header, partitions, ops, real pool, phase terms, slots; the pool
  * is stored as doubles) into buf (cap bytes); *size receives the length. */
 int qsv_plan_op_program(const qsv_plan *plan, int index, void *buf, size_t cap, size_t *size);
+/* Host-only: the HIP source of the kernel that op `index` (an LDS pass)
+ * compiles to when the plan is built with opts->jit, NUL-terminated, into
+ * buf (cap bytes); *size receives the length including the NUL. */
+int qsv_plan_op_source(const qsv_plan *plan, int index, char *buf, size_t cap, size_t *size);
 void qsv_plan_destroy(qsv_plan *plan);
 
 /* Dense fused block on FP32 matrix cores (complex64 only): Y = G X with X

@@ -229,9 +229,9 @@ class Plan:
             pass
 
 
-def qsv_plan_create(n, dtype, circuit, mode=PLAN_PER_GATE, kmax=2, local_bits=0, use_mfma=1):
+def qsv_plan_create(n, dtype, circuit, mode=PLAN_PER_GATE, kmax=2, local_bits=0, use_mfma=1, jit=0):
     arr, keep = gates_to_c(circuit)
-    opts = QsvPlanOptions(int(mode), int(kmax), int(local_bits), int(use_mfma))
+    opts = QsvPlanOptions(int(mode), int(kmax), int(local_bits), int(use_mfma), int(jit))
     h = ctypes.c_void_p()
     check("qsv_plan_create", load().qsv_plan_create(int(n), int(dtype), arr, len(circuit), ctypes.byref(opts),
                                                     ctypes.byref(h)))
@@ -277,6 +277,15 @@ def qsv_plan_op_program(plan, index):
     buf = ctypes.create_string_buffer(size.value)
     check("qsv_plan_op_program", load().qsv_plan_op_program(plan._h, int(index), buf, size.value, ctypes.byref(size)))
     return buf.raw[:size.value]
+
+
+def qsv_plan_op_source(plan, index):
+    """HIP source of the compiled kernel of LDS-pass op `index` (host only)."""
+    size = ctypes.c_size_t(0)
+    check("qsv_plan_op_source", load().qsv_plan_op_source(plan._h, int(index), None, 0, ctypes.byref(size)))
+    buf = ctypes.create_string_buffer(size.value)
+    check("qsv_plan_op_source", load().qsv_plan_op_source(plan._h, int(index), buf, size.value, ctypes.byref(size)))
+    return buf.value.decode()
 
 
 def qsv_plan_destroy(plan):

@@ -34,12 +34,13 @@ class QsvGate(ctypes.Structure):
 
 class QsvPlanOptions(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("kmax", ctypes.c_int), ("local_bits", ctypes.c_int),
-                ("use_mfma", ctypes.c_int)]
+                ("use_mfma", ctypes.c_int), ("jit", ctypes.c_int)]
 
 
 class QsvPlanStats(ctypes.Structure):
     _fields_ = [("n_launches", ctypes.c_int), ("n_gate_ops", ctypes.c_int), ("n_blocks", ctypes.c_int),
                 ("n_mfma_blocks", ctypes.c_int), ("n_passes", ctypes.c_int), ("mode_used", ctypes.c_int),
+                ("n_jit_passes", ctypes.c_int),
                 ("bytes", ctypes.c_double), ("flops", ctypes.c_double), ("predicted_s", ctypes.c_double)]
 
 
@@ -73,6 +74,7 @@ SIGNATURES = {
     "qsv_plan_execute_ops": ([_vp, _vp, _i, _i, _vp], _i),
     "qsv_plan_op_info": ([_vp, _i, _vp, _vp, _vp], _i),
     "qsv_plan_op_program": ([_vp, _i, _vp, ctypes.c_size_t, _vp], _i),
+    "qsv_plan_op_source": ([_vp, _i, _vp, ctypes.c_size_t, _vp], _i),
     "qsv_apply_block": ([_vp, _i, _i, _vp, _vp, _i, _vp], _i),
     "qsv_run_pass": ([_vp, _i, _i, _vp, _i, _vp, _i, _vp], _i),
     "qsv_probabilities": ([_vp, _i, _i, _vp, _i, _vp, _vp], _i),

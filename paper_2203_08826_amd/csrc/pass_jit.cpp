@@ -1,0 +1,571 @@
+// Pass programs compiled into kernels of their own.
+//
+// The pass kernel of pass_kernel.hip interprets a program: every op of every
+// chunk dispatches on the op kind, loads its constants and moves the
+// register tile between the registers of the switch cases.  Here a program
+// is instead turned into HIP source for one kernel, compiled at plan
+// creation with hiprtc and loaded on first use: the op sequence, the
+// register/thread assignments, the gate matrices and the constant phase
+// factors become literals.  Register-bit controls become compile-time pair
+// selections, zero matrix entries drop out, a row with a single unit entry
+// becomes a register move, and the per-thread LDS and global offsets are
+// computed once per kernel.  The semantics are those of the interpreted
+// kernel op for op (same ops, same tables in the program's pool, same
+// phase-term grouping); only the arithmetic order may differ.
+#include <hip/hiprtc.h>
+
+#include <cinttypes>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "plan_internal.h"
+
+namespace qsv {
+
+struct JitModule {
+    std::vector<char> code;                 // code object for gfx950
+    std::mutex mu;
+    struct Loaded {
+        hipModule_t mod = nullptr;
+        hipFunction_t fn = nullptr;
+        int grid_per_cu = 0;
+    };
+    std::map<int, Loaded> dev;              // per device, loaded on first launch
+    ~JitModule() {
+        for (auto &kv : dev)
+            if (kv.second.mod) {
+                int cur = 0;
+                (void)hipGetDevice(&cur);
+                (void)hipSetDevice(kv.first);
+                (void)hipDeviceSynchronize();   // no launch of this module may still run
+                (void)hipModuleUnload(kv.second.mod);
+                (void)hipSetDevice(cur);
+            }
+    }
+};
+
+namespace {
+
+const char *JIT_KERNEL_NAME = "qsv_pass_jit";
+
+// ---------------------------------------------------------------- source generation
+
+std::string fmt(const char *f, ...) __attribute__((format(printf, 1, 2)));
+std::string fmt(const char *f, ...) {
+    va_list ap, aq;
+    va_start(ap, f);
+    va_copy(aq, ap);
+    const int n = vsnprintf(nullptr, 0, f, ap);
+    va_end(ap);
+    std::string out(n > 0 ? (size_t)n : 0, '\0');
+    if (n > 0) vsnprintf(&out[0], (size_t)n + 1, f, aq);
+    va_end(aq);
+    return out;
+}
+
+uint32_t swz(uint32_t l) { return l ^ (((l >> 4) ^ (l >> 8) ^ (l >> 12)) & 15u); }
+
+class Gen {
+  public:
+    Gen(const PassProgram &p, int dtype)
+        : P(p), f32(dtype == QSV_C64), NR(1 << p.RB), pool_offset(((const PassHeaderDev *)p.blob.data())->off_pool) {}
+    std::string source();
+
+  private:
+    const PassProgram &P;
+    const bool f32;
+    const int NR;
+    const int pool_offset;   // byte offset of the real pool in the serialised program
+    std::string s;
+    int uid = 0;
+
+    void ln(const std::string &x) { s += x, s += '\n'; }
+    double R(double v) const { return f32 ? (double)(float)v : v; }   // value as the kernel's real type holds it
+    std::string lit(double v) const {
+        char buf[64];
+        if (f32) snprintf(buf, sizeof(buf), "%af", (double)(float)v);
+        else snprintf(buf, sizeof(buf), "%a", v);
+        return buf;
+    }
+    std::string u64(uint64_t v) const { return fmt("0x%" PRIx64 "ull", v); }
+
+    // x or y component of sum_s c_s * a_s (c_s complex literals, a_s C variables)
+    std::string comb(const std::vector<std::pair<std::pair<double, double>, std::string>> &terms, bool y) const;
+    void gate(const PassOpDev &op, const std::vector<int> &bits, const std::vector<double> &M, bool real);
+    void phase(const PassOpDev &op, int sk);   // multiplies v[j] (j with bit sk clear: v[j | 2^sk]) by f_j
+    std::string thread_offset(const PassPartition &part, const int *pos, bool global) const;
+};
+
+std::string Gen::comb(const std::vector<std::pair<std::pair<double, double>, std::string>> &terms, bool y) const {
+    std::string e;
+    auto add = [&](double c, const std::string &var) {
+        if (c == 0.0) return;
+        if (c == 1.0) e += (e.empty() ? "" : " + ") + var;
+        else if (c == -1.0) e += (e.empty() ? "-" : " - ") + var;
+        else e += (e.empty() ? "" : " + ") + lit(c) + " * " + var;
+    };
+    for (auto &t : terms) {
+        const double re = R(t.first.first), im = R(t.first.second);
+        if (!y) {
+            add(re, t.second + ".x");
+            add(-im, t.second + ".y");
+        } else {
+            add(re, t.second + ".y");
+            add(im, t.second + ".x");
+        }
+    }
+    return e.empty() ? std::string("(R)0") : e;
+}
+
+// Global (or local) offset of the thread part of a partition: sum over the
+// thread bits u of bit u of t shifted to its position.
+std::string Gen::thread_offset(const PassPartition &part, const int *pos, bool global) const {
+    std::string e;
+    for (int u = 0; u < PASS_THREAD_BITS; ++u) {
+        const int p = pos ? pos[part.thr_l[u]] : part.thr_l[u];
+        if (!e.empty()) e += " | ";
+        if (global) e += fmt("((unsigned long long)((t >> %d) & 1u) << %d)", u, p);
+        else e += fmt("(((t >> %d) & 1u) << %d)", u, p);
+    }
+    return "(" + e + ")";
+}
+
+// One- or two-qubit gate on register bits (bits[0] = the matrix index MSB).
+void Gen::gate(const PassOpDev &op, const std::vector<int> &bits, const std::vector<double> &M, bool real) {
+    const int k = (int)bits.size(), d = 1 << k;
+    const bool tok = op.ct != 0 || op.cn != 0;
+    if (tok) ln(fmt("        { const bool tk = ((t & %uu) == %uu) && ((base & %s) == %s);", op.ct, op.ct,
+                    u64(op.cn).c_str(), u64(op.cn).c_str()));
+    else ln("        {");
+    uint32_t gm = 0;
+    for (int b : bits) gm |= 1u << b;
+    for (int j = 0; j < NR; ++j) {
+        if (j & gm) continue;
+        if (((uint32_t)j & op.cj) != op.cj) continue;
+        std::vector<int> idx(d);
+        for (int r = 0; r < d; ++r) {
+            int x = j;
+            for (int q = 0; q < k; ++q)
+                if ((r >> (k - 1 - q)) & 1) x |= 1 << bits[q];
+            idx[r] = x;
+        }
+        std::string body = "            {";
+        for (int r = 0; r < d; ++r) body += fmt(" const C a%d = v[%d];", r, idx[r]);
+        ln(body);
+        for (int r = 0; r < d; ++r) {
+            std::vector<std::pair<std::pair<double, double>, std::string>> terms;
+            bool unit_self = true;
+            for (int c = 0; c < d; ++c) {
+                double re, im;
+                if (real) re = M[r * d + c], im = 0.0;
+                else re = M[2 * (r * d + c)], im = M[2 * (r * d + c) + 1];
+                const double rr = R(re), ri = R(im);
+                if (rr == 0.0 && ri == 0.0) continue;
+                if (!(c == r && rr == 1.0 && ri == 0.0)) unit_self = false;
+                terms.push_back({{re, im}, fmt("a%d", c)});
+            }
+            if (unit_self && terms.size() == 1) continue;   // row of the identity
+            const std::string ex = comb(terms, false), ey = comb(terms, true);
+            if (tok)
+                ln(fmt("              v[%d].x = tk ? (R)(%s) : a%d.x; v[%d].y = tk ? (R)(%s) : a%d.y;", idx[r],
+                       ex.c_str(), r, idx[r], ey.c_str(), r));
+            else ln(fmt("              v[%d].x = %s; v[%d].y = %s;", idx[r], ex.c_str(), idx[r], ey.c_str()));
+        }
+        ln("            }");
+    }
+    ln("        }");
+}
+
+// Phase factors of an op (see PassOpDev), applied to the register tile.
+void Gen::phase(const PassOpDev &op, int sk) {
+    const int RB = P.RB;
+    const int id = uid++;
+    ln("        {");
+    // F_g for the groups that vary per thread or chunk
+    std::vector<bool> var(RB + 1, false);
+    const int s0 = op.sl[0], s1 = op.sl[RB + 1];
+    if (s1 > s0) {
+        // chunk-dependent slot sums (uniform), one per lane, one sincos
+        ln("          unsigned long long sph = 0;");
+        for (int sI = s0; sI < s1; ++sI) {
+            const PassSlotDev &sd = P.slots[sI];
+            std::string e;
+            for (int kI = sd.begin; kI < sd.end; ++kI) {
+                const PassTermDev &tm = P.terms[kI];
+                if (tm.mn == 0) e += fmt(" + %s", u64(tm.theta).c_str());
+                else e += fmt(" + (((base & %s) == %s) ? %s : 0ull)", u64(tm.mn).c_str(), u64(tm.mn).c_str(),
+                              u64(tm.theta).c_str());
+            }
+            ln(fmt("          if (lane == %d) sph = 0ull%s;", sI - s0, e.c_str()));
+        }
+        ln("          const C se = expi(sph);");
+    }
+    for (int g = 0; g <= RB; ++g) {
+        const bool has_tab = op.tab[g] >= 0, has_sl = op.sl[g + 1] > op.sl[g];
+        if (!has_tab && !has_sl) continue;
+        var[g] = true;
+        if (has_tab) ln(fmt("          C F%d = ((const C *)(pool + %d))[t];", g, op.tab[g]));
+        else ln(fmt("          C F%d; F%d.x = (R)1; F%d.y = (R)0;", g, g, g));
+        for (int sI = op.sl[g]; sI < op.sl[g + 1]; ++sI) {
+            const uint32_t mt = P.slots[sI].mt;
+            if (mt == 0) ln(fmt("          F%d = cm(F%d, rdl(se, %d));", g, g, sI - s0));
+            else ln(fmt("          { const C e = rdl(se, %d); if ((t & %uu) == %uu) F%d = cm(F%d, e); }", sI - s0, mt,
+                        mt, g, g));
+        }
+    }
+    // h_j = F_0 * prod_{i in j} F_{1+i}; "one" entries are tracked on the host
+    std::vector<int> h_one(NR, 1);
+    std::vector<std::string> h(NR);
+    if (var[0]) {
+        h[0] = "F0";
+        h_one[0] = 0;
+    }
+    for (int top = 0; top < RB; ++top) {
+        if (top == sk) continue;
+        for (int rest = 0; rest < (1 << top); ++rest) {
+            if (sk >= 0 && ((rest >> sk) & 1)) continue;
+            const int j = rest | (1 << top);
+            if (!var[1 + top]) {
+                h[j] = h[rest];
+                h_one[j] = h_one[rest];
+            } else if (h_one[rest]) {
+                h[j] = fmt("F%d", 1 + top);
+                h_one[j] = 0;
+            } else {
+                ln(fmt("          const C h%d_%d = cm(%s, F%d);", id, j, h[rest].c_str(), 1 + top));
+                h[j] = fmt("h%d_%d", id, j);
+                h_one[j] = 0;
+            }
+        }
+    }
+    for (int j = 0; j < NR; ++j) {
+        if (sk >= 0 && ((j >> sk) & 1)) continue;
+        const int tj = sk >= 0 ? (j | (1 << sk)) : j;   // the amplitude the factor multiplies
+        double cre = 1.0, cim = 0.0;
+        if (op.fc >= 0) {
+            cre = R(P.pool[op.fc + 2 * j]);
+            cim = R(P.pool[op.fc + 2 * j + 1]);
+        }
+        const bool c_one = cre == 1.0 && cim == 0.0;
+        if (!h_one[j]) ln(fmt("          v[%d] = cm(v[%d], %s);", tj, tj, h[j].c_str()));
+        if (!c_one) ln(fmt("          v[%d] = cml(v[%d], %s, %s);", tj, tj, lit(cre).c_str(), lit(cim).c_str()));
+        // general terms
+        std::string e;
+        for (int kI = op.gen_b; kI < op.gen_e; ++kI) {
+            const PassTermDev &tm = P.terms[kI];
+            if (((uint32_t)j & tm.mj) != tm.mj) continue;
+            e += fmt(" + ((((t & %uu) == %uu) && ((base & %s) == %s)) ? %s : 0ull)", tm.mt, tm.mt,
+                     u64(tm.mn).c_str(), u64(tm.mn).c_str(), u64(tm.theta).c_str());
+        }
+        if (!e.empty()) ln(fmt("          v[%d] = cm(v[%d], expi(0ull%s));", tj, tj, e.c_str()));
+    }
+    ln("        }");
+}
+
+std::string Gen::source() {
+    const int L = P.L, RB = P.RB;
+    const bool PF = f32 ? RB <= 4 : RB <= 3;
+    bool any_exchange = false;
+    for (auto &op : P.ops)
+        if (op.kind == POP_EXCHANGE) any_exchange = true;
+    bool relabel = false;
+    for (int l = 0; l < L; ++l)
+        if (P.out_pos[l] != P.local_sorted[l]) relabel = true;
+    if (any_exchange) relabel = false;
+
+    ln(f32 ? "typedef float R;" : "typedef double R;");
+    ln("struct __attribute__((aligned(2 * sizeof(R)))) C { R x, y; };");
+    ln("__device__ __forceinline__ C cm(C a, C b) { C r; r.x = a.x * b.x - a.y * b.y; r.y = a.x * b.y + a.y * b.x; "
+       "return r; }");
+    ln("__device__ __forceinline__ C cml(C a, R re, R im) { C r; r.x = a.x * re - a.y * im; r.y = a.x * im + a.y * re; "
+       "return r; }");
+    if (f32) {
+        ln("__device__ __forceinline__ C expi(unsigned long long ph) {");
+        ln("    const float x = (float)(int)(unsigned)(ph >> 32) * 2.3283064365386963e-10f;");
+        ln("    C r; sincospif(2.0f * x, &r.y, &r.x); return r; }");
+        ln("__device__ __forceinline__ C rdl(C v, int l) { C r;");
+        ln("    r.x = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v.x), l));");
+        ln("    r.y = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v.y), l)); return r; }");
+    } else {
+        ln("__device__ __forceinline__ C expi(unsigned long long ph) {");
+        ln("    const double x = (double)(long long)ph * 5.421010862427522e-20;");
+        ln("    C r; sincospi(2.0 * x, &r.y, &r.x); return r; }");
+        ln("__device__ __forceinline__ double rdl1(double v, int l) {");
+        ln("    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);");
+        ln("    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);");
+        ln("    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);");
+        ln("    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo); }");
+        ln("__device__ __forceinline__ C rdl(C v, int l) { C r; r.x = rdl1(v.x, l); r.y = rdl1(v.y, l); return r; }");
+    }
+    ln("__device__ __forceinline__ void lbar() {");
+    ln("    __builtin_amdgcn_fence(__ATOMIC_RELEASE, \"workgroup\", \"local\");");
+    ln("    __builtin_amdgcn_s_barrier();");
+    ln("    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, \"workgroup\", \"local\"); }");
+    ln("__device__ __forceinline__ unsigned swz(unsigned l) { return l ^ (((l >> 4) ^ (l >> 8) ^ (l >> 12)) & 15u); }");
+    ln("");
+    ln(fmt("extern \"C\" __global__ void __launch_bounds__(256) %s(C *__restrict__ psi, const unsigned char "
+           "*__restrict__ prog, unsigned long long nchunks) {",
+           JIT_KERNEL_NAME));
+    if (any_exchange) ln(fmt("    __shared__ C lds[%d];", 1 << L));
+    ln(fmt("    const R *pool = (const R *)(prog + %d);", pool_offset));
+    ln("    (void)pool;");
+    ln("    const unsigned t = threadIdx.x;");
+    ln("    const int lane = (int)(t & 63u);");
+    ln("    (void)lane;");
+    // per-thread offsets, once per kernel
+    int in_pos[PASS_MAX_L], out_pos[PASS_MAX_L];
+    for (int l = 0; l < L; ++l) {
+        in_pos[l] = P.local_sorted[l];
+        out_pos[l] = P.out_pos[l];
+    }
+    ln("    const unsigned long long lt_in = " + thread_offset(P.parts[P.load_part], in_pos, true) + ";");
+    int cur = P.load_part;
+    for (auto &op : P.ops)
+        if (op.kind == POP_EXCHANGE) cur = op.a;
+    const int final_part = cur;
+    ln("    const unsigned long long lt_out = " + thread_offset(P.parts[final_part], out_pos, true) + ";");
+    if (any_exchange)
+        for (size_t pi = 0; pi < P.parts.size(); ++pi)
+            ln(fmt("    const unsigned xo%zu = swz(%s) * (unsigned)sizeof(C);", pi,
+                   thread_offset(P.parts[pi], nullptr, false).c_str()));
+    // chunk base: the chunk index with zeros inserted at the local bits
+    std::string cb = "    auto chunk_base = [&](unsigned long long c) { unsigned long long b = c, lo;";
+    for (int l = 0; l < L; ++l)
+        cb += fmt(" lo = b & %s; b = lo | ((b ^ lo) << 1);", u64((1ull << P.local_sorted[l]) - 1ull).c_str());
+    cb += " return b; };";
+    ln(cb);
+    // register offsets of the load and store partitions
+    auto reg_off = [&](const PassPartition &part, const int *pos, int j) {
+        uint64_t o = 0;
+        for (int i = 0; i < RB; ++i)
+            if ((j >> i) & 1) o |= 1ull << pos[part.reg_l[i]];
+        return o;
+    };
+    std::string ld = "    auto load_chunk = [&](C *dst, unsigned long long b) { const C *p = psi + (b | lt_in);";
+    for (int j = 0; j < NR; ++j) ld += fmt(" dst[%d] = p[%s];", j, u64(reg_off(P.parts[P.load_part], in_pos, j)).c_str());
+    ld += " };";
+    ln(ld);
+    ln(fmt("    C v[%d];", NR));
+    ln("    unsigned long long c = blockIdx.x;");
+    if (PF) ln("    if (c < nchunks) load_chunk(v, chunk_base(c));");
+    ln("    for (; c < nchunks; c += gridDim.x) {");
+    ln("        const unsigned long long base = chunk_base(c);");
+    if (PF) {
+        ln(fmt("        C vn[%d];", NR));
+        ln("        const unsigned long long cn = c + gridDim.x;");
+        ln("        if (cn < nchunks) load_chunk(vn, chunk_base(cn));");
+    } else {
+        ln("        load_chunk(v, base);");
+    }
+    cur = P.load_part;
+    for (size_t o = 0; o < P.ops.size(); ++o) {
+        const PassOpDev &op = P.ops[o];
+        ln(fmt("        // op %zu", o));
+        switch (op.kind) {
+        case POP_G1:
+        case POP_G1R: {
+            if (op.pre) phase(op, op.a);
+            std::vector<double> M;
+            const int cnt = op.kind == POP_G1 ? 8 : 4;
+            for (int e = 0; e < cnt; ++e) M.push_back(P.pool[op.mat + e]);
+            gate(op, {op.a}, M, op.kind == POP_G1R);
+            break;
+        }
+        case POP_G2: {
+            std::vector<double> M(P.pool.begin() + op.mat, P.pool.begin() + op.mat + 32);
+            gate(op, {op.a, op.b}, M, false);
+            break;
+        }
+        case POP_PHASE: phase(op, -1); break;
+        case POP_EXCHANGE: {
+            const PassPartition &A = P.parts[cur], &B = P.parts[op.a];
+            const int csz = f32 ? 8 : 16;
+            ln("        lbar();");
+            std::string w = "       ";
+            for (int j = 0; j < NR; ++j) {
+                uint32_t l = 0;
+                for (int i = 0; i < RB; ++i)
+                    if ((j >> i) & 1) l |= 1u << A.reg_l[i];
+                w += fmt(" *(C *)((char *)lds + (xo%d ^ %uu)) = v[%d];", cur, swz(l) * csz, j);
+            }
+            ln(w);
+            ln("        lbar();");
+            std::string r = "       ";
+            for (int j = 0; j < NR; ++j) {
+                uint32_t l = 0;
+                for (int i = 0; i < RB; ++i)
+                    if ((j >> i) & 1) l |= 1u << B.reg_l[i];
+                r += fmt(" v[%d] = *(const C *)((const char *)lds + (xo%d ^ %uu));", j, op.a, swz(l) * csz);
+            }
+            ln(r);
+            cur = op.a;
+            break;
+        }
+        default: break;
+        }
+    }
+    if (relabel) ln("        __syncthreads();");
+    std::string st = "        { C *p = psi + (base | lt_out);";
+    for (int j = 0; j < NR; ++j) st += fmt(" p[%s] = v[%d];", u64(reg_off(P.parts[final_part], out_pos, j)).c_str(), j);
+    st += " }";
+    ln(st);
+    if (PF) {
+        std::string cp = "       ";
+        for (int j = 0; j < NR; ++j) cp += fmt(" v[%d] = vn[%d];", j, j);
+        ln(cp);
+    }
+    ln("    }");
+    ln("}");
+    return s;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- compilation and launch
+
+namespace {
+
+std::mutex cache_mu;
+std::unordered_map<std::string, std::shared_ptr<JitModule>> cache;   // by source text
+constexpr size_t CACHE_MAX = 512;
+
+int compile_source(const std::string &src, std::vector<char> &code, std::string &err) {
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.c_str(), "qsv_pass.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS) {
+        err = "hiprtcCreateProgram failed";
+        return -1;
+    }
+    // the same code-generation settings as the library's own device code
+    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+                          "-packed-fp32-ops", "-mllvm", "-simplifycfg-sink-common=false"};
+    const hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts);
+    if (r != HIPRTC_SUCCESS) {
+        size_t ls = 0;
+        hiprtcGetProgramLogSize(prog, &ls);
+        std::string log(ls, '\0');
+        if (ls) hiprtcGetProgramLog(prog, &log[0]);
+        err = std::string(hiprtcGetErrorString(r)) + ": " + log.substr(0, 2000);
+        hiprtcDestroyProgram(&prog);
+        return -1;
+    }
+    size_t n = 0;
+    hiprtcGetCodeSize(prog, &n);
+    code.resize(n);
+    hiprtcGetCode(prog, code.data());
+    hiprtcDestroyProgram(&prog);
+    return 0;
+}
+
+}  // namespace
+
+std::string pass_jit_source(const PassProgram &prog, int dtype) {
+    Gen g(prog, dtype);
+    return g.source();
+}
+
+int jit_compile_plan(qsv_plan *p) {
+    std::vector<PassProgram *> progs;
+    for (auto &op : p->ops)
+        if (op.kind == PlanOp::PASS && !op.pass->jit) progs.push_back(op.pass.get());
+    if (progs.empty()) return QSV_OK;
+    std::vector<std::string> srcs(progs.size());
+    std::vector<std::shared_ptr<JitModule>> mods(progs.size());
+    std::vector<size_t> todo;
+    {
+        std::lock_guard<std::mutex> lk(cache_mu);
+        for (size_t i = 0; i < progs.size(); ++i) {
+            srcs[i] = pass_jit_source(*progs[i], p->dtype);
+            auto it = cache.find(srcs[i]);
+            if (it != cache.end()) mods[i] = it->second;
+            else todo.push_back(i);
+        }
+    }
+    // distinct sources compile side by side
+    std::map<std::string, size_t> first;
+    std::vector<size_t> uniq;
+    for (size_t i : todo)
+        if (first.emplace(srcs[i], i).second) uniq.push_back(i);
+    std::vector<std::string> errs(uniq.size());
+    std::vector<std::vector<char>> codes(uniq.size());
+    size_t nth = std::max<size_t>(1, std::min<size_t>(uniq.size(), std::min(16u, std::max(1u, std::thread::hardware_concurrency()))));
+    std::vector<std::thread> th;
+    std::mutex next_mu;
+    size_t next = 0;
+    for (size_t w = 0; w < nth; ++w)
+        th.emplace_back([&] {
+            for (;;) {
+                size_t u;
+                {
+                    std::lock_guard<std::mutex> lk(next_mu);
+                    if (next >= uniq.size()) return;
+                    u = next++;
+                }
+                if (compile_source(srcs[uniq[u]], codes[u], errs[u])) codes[u].clear();
+            }
+        });
+    for (auto &x : th) x.join();
+    for (size_t u = 0; u < uniq.size(); ++u)
+        if (codes[u].empty()) return fail(QSV_ERR_UNSUPPORTED, "pass kernel compilation failed: " + errs[u]);
+    {
+        std::lock_guard<std::mutex> lk(cache_mu);
+        if (cache.size() + uniq.size() > CACHE_MAX) cache.clear();   // plans keep their own modules
+        for (size_t u = 0; u < uniq.size(); ++u) {
+            auto m = std::make_shared<JitModule>();
+            m->code.swap(codes[u]);
+            cache[srcs[uniq[u]]] = m;
+        }
+        for (size_t i : todo) mods[i] = cache[srcs[i]];
+    }
+    for (size_t i = 0; i < progs.size(); ++i) progs[i]->jit = mods[i];
+    p->stats.n_jit_passes = 0;
+    for (auto &op : p->ops)
+        if (op.kind == PlanOp::PASS && op.pass->jit) p->stats.n_jit_passes++;
+    return QSV_OK;
+}
+
+int launch_pass_jit(void *state, int n, int dtype, const PassProgram &prog, hipStream_t s) {
+    JitModule &jm = *prog.jit;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipFunction_t fn;
+    int per_cu;
+    {
+        std::lock_guard<std::mutex> lk(jm.mu);
+        JitModule::Loaded &ld = jm.dev[dev];
+        if (!ld.mod) {
+            if ((e = hipModuleLoadData(&ld.mod, jm.code.data())) != hipSuccess) {
+                ld.mod = nullptr;
+                return hip_fail(e, "loading a compiled pass kernel");
+            }
+            if ((e = hipModuleGetFunction(&ld.fn, ld.mod, JIT_KERNEL_NAME)) != hipSuccess)
+                return hip_fail(e, "finding the compiled pass kernel");
+            int b = 0;
+            if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&b, ld.fn, 256, 0) != hipSuccess || b < 1) b = 1;
+            ld.grid_per_cu = b;
+        }
+        fn = ld.fn;
+        per_cu = ld.grid_per_cu;
+    }
+    StagingSlot slot;
+    int st = upload_pass_program(prog, dtype, s, &slot);
+    if (st) return st;
+    uint64_t nchunks = 1ull << (n - prog.L);
+    const bool pf = dtype == QSV_C64 ? prog.RB <= 4 : prog.RB <= 3;
+    uint64_t g = pf ? (uint64_t)per_cu * device_sm_count() : std::min<uint64_t>(nchunks, 1ull << 20);
+    if (g > nchunks) g = nchunks;
+    void *dprog = slot.dev;
+    void *args[] = {&state, &dprog, &nchunks};
+    e = hipModuleLaunchKernel(fn, (unsigned)g, 1, 1, 256, 1, 1, 0, s, args, nullptr);
+    staging_release(slot, s);
+    if (e != hipSuccess) return hip_fail(e, "compiled pass kernel launch");
+    return QSV_OK;
+}
+
+}  // namespace qsv

@@ -540,22 +540,34 @@ static void launch_k_pass(void *state, const uint8_t *dprog, uint64_t nchunks, h
                        nchunks);
 }
 
-int launch_pass_program(void *state, int n, int dtype, const PassProgram &prog, hipStream_t s) {
+// Copies a serialised program (pool in the state's real type) into a staging
+// slot and uploads it on stream s; the caller releases the slot after the
+// launch that reads it.
+int upload_pass_program(const PassProgram &prog, int dtype, hipStream_t s, StagingSlot *slot) {
     const size_t bytes = prog.blob.size();
     if (bytes > staging_slot_bytes()) return fail(QSV_ERR_UNSUPPORTED, "pass program larger than a staging slot");
-    StagingSlot slot;
-    int st = staging_acquire(bytes, &slot);
+    int st = staging_acquire(bytes, slot);
     if (st) return st;
-    std::memcpy(slot.host, prog.blob.data(), bytes);
+    std::memcpy(slot->host, prog.blob.data(), bytes);
     const PassHeaderDev *h = (const PassHeaderDev *)prog.blob.data();
     if (dtype == QSV_C64) {
-        float *pool = (float *)((char *)slot.host + h->off_pool);
+        float *pool = (float *)((char *)slot->host + h->off_pool);
         for (size_t i = 0; i < prog.pool.size(); ++i) pool[i] = (float)prog.pool[i];
     } else {
-        double *pool = (double *)((char *)slot.host + h->off_pool);
+        double *pool = (double *)((char *)slot->host + h->off_pool);
         for (size_t i = 0; i < prog.pool.size(); ++i) pool[i] = prog.pool[i];
     }
-    if ((st = staging_upload(slot, bytes, s))) return st;
+    if ((st = staging_upload(*slot, bytes, s))) {
+        staging_release(*slot, s);
+        return st;
+    }
+    return QSV_OK;
+}
+
+int launch_pass_program(void *state, int n, int dtype, const PassProgram &prog, hipStream_t s) {
+    StagingSlot slot;
+    int st = upload_pass_program(prog, dtype, s, &slot);
+    if (st) return st;
     const uint64_t nchunks = 1ull << (n - prog.L);
     const uint8_t *d = (const uint8_t *)slot.dev;
     if (dtype == QSV_C64) {

@@ -201,7 +201,9 @@ int execute_op(const qsv_plan *p, const PlanOp &op, void *state, hipStream_t s) 
     case PlanOp::GATE: return launch_gate(state, p->dtype, op.analysis, s);
     case PlanOp::MFMA_BLOCK:
         return launch_block_mfma(state, p->n, op.matrix.data(), op.qubits.data(), (int)op.qubits.size(), s);
-    case PlanOp::PASS: return launch_pass_program(state, p->n, p->dtype, *op.pass, s);
+    case PlanOp::PASS:
+        return op.pass->jit ? launch_pass_jit(state, p->n, p->dtype, *op.pass, s)
+                            : launch_pass_program(state, p->n, p->dtype, *op.pass, s);
     case PlanOp::PERM: return launch_bitperm(state, p->n, p->dtype, op.sigma, s);
     }
     return fail(QSV_ERR_ARG, "internal: unknown op kind");
@@ -226,7 +228,7 @@ int qsv_plan_create(int n, int dtype, const qsv_gate *gates, int ngates, const q
     if (!out) return fail(QSV_ERR_NULL, "out is NULL");
     *out = nullptr;
     if (ngates < 0 || (ngates > 0 && !gates)) return fail(QSV_ERR_NULL, "gates is NULL");
-    qsv_plan_options o = {QSV_PLAN_PER_GATE, 2, 0, 1};
+    qsv_plan_options o = {QSV_PLAN_PER_GATE, 2, 0, 1, 0};
     if (opts) o = *opts;
     if (o.mode < 0 || o.mode > QSV_PLAN_LEARNED) return fail(QSV_ERR_ARG, "unknown plan mode");
     if (o.kmax == 0) o.kmax = 2;
@@ -262,6 +264,7 @@ int qsv_plan_create(int n, int dtype, const qsv_gate *gates, int ngates, const q
     case QSV_PLAN_LEARNED: st = build_learned(p.get()); break;
     }
     if (st) return st;
+    if (o.jit && (st = jit_compile_plan(p.get()))) return st;
     if (p->stats.mode_used == 0 && o.mode != QSV_PLAN_LEARNED) p->stats.mode_used = o.mode;
     finish_stats(p.get());
     *out = p.release();
@@ -321,6 +324,20 @@ int qsv_plan_op_program(const qsv_plan *plan, int index, void *buf, size_t cap, 
     if (buf) {
         if (cap < blob.size()) return fail(QSV_ERR_ARG, "buffer too small");
         std::memcpy(buf, blob.data(), blob.size());
+    }
+    return QSV_OK;
+}
+
+int qsv_plan_op_source(const qsv_plan *plan, int index, char *buf, size_t cap, size_t *size) {
+    if (!plan || !size) return fail(QSV_ERR_NULL, "NULL argument");
+    if (index < 0 || index >= (int)plan->ops.size()) return fail(QSV_ERR_ARG, "op index out of bounds");
+    const PlanOp &op = plan->ops[index];
+    if (op.kind != PlanOp::PASS) return fail(QSV_ERR_ARG, "op is not an LDS pass");
+    const std::string src = pass_jit_source(*op.pass, plan->dtype);
+    *size = src.size() + 1;
+    if (buf) {
+        if (cap < src.size() + 1) return fail(QSV_ERR_ARG, "buffer too small");
+        std::memcpy(buf, src.c_str(), src.size() + 1);
     }
     return QSV_OK;
 }

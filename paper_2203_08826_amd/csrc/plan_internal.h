@@ -92,6 +92,8 @@ struct PassHeaderDev {
     int32_t relabel;               // 1: some thread stores where another loaded
 };
 
+struct JitModule;   // a pass program compiled into a kernel of its own (pass_jit.cpp)
+
 // Host-side pass program (what the planner emits, before serialisation).
 struct PassProgram {
     int L = 0;
@@ -106,10 +108,14 @@ struct PassProgram {
     std::vector<PassSlotDev> slots;
     int n_gates = 0;                      // circuit gates folded into this pass
     std::vector<uint8_t> blob;            // serialised program
+    std::shared_ptr<JitModule> jit;       // compiled kernel, when the plan asked for one
     void serialise();
 };
 
+int upload_pass_program(const PassProgram &prog, int dtype, hipStream_t s, StagingSlot *slot);
 int launch_pass_program(void *state, int n, int dtype, const PassProgram &prog, hipStream_t s);
+int launch_pass_jit(void *state, int n, int dtype, const PassProgram &prog, hipStream_t s);
+std::string pass_jit_source(const PassProgram &prog, int dtype);
 int launch_bitperm(void *state, int n, int dtype, const std::vector<int> &sigma, hipStream_t s);
 
 // ---------------------------------------------------------------- plans
@@ -149,6 +155,7 @@ int plan_add_block_op(qsv_plan *p, const std::vector<int> &qubits, const std::ve
 int build_greedy(qsv_plan *p, int kmax, bool allow_mfma);
 int build_passes(qsv_plan *p, int local_bits);
 int build_learned(qsv_plan *p);
+int jit_compile_plan(qsv_plan *p);   // compiles every pass of the plan (hiprtc)
 void finish_stats(qsv_plan *p);
 int execute_plan(const qsv_plan *p, void *state, hipStream_t s);
 int execute_op(const qsv_plan *p, const PlanOp &op, void *state, hipStream_t s);

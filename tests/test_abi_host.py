@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
     for s in syms:
         assert hasattr(lib, s), s
         assert s in qsv._abi.SIGNATURES, s
-    assert qsv.qsv_abi_version() == 1
+    assert qsv.qsv_abi_version() == 2
 
 
 def test_validation_codes():
@@ -96,3 +96,23 @@ def test_library_gate_matrices_match_oracle():
     d = W.random_phases(2, rng)
     g = {"name": "DIAG", "targets": [0, 1], "controls": [], "diag": d}
     assert np.array_equal(qsv.qsv_gate_matrix(g), np.diag(d))
+
+
+def test_pass_compilation_on_host():
+    """jit=1 compiles every LDS pass at plan creation with the host compiler
+    only (no device needed); the generated source turns permutation rows into
+    plain moves and keeps the interpreted program's op sequence."""
+    n = 12
+    circ = W.qft(n)
+    p = qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_PASSES, jit=1)
+    st = p.stats()
+    assert st["n_passes"] >= 1 and st["n_jit_passes"] >= 1
+    src = qsv.qsv_plan_op_source(p, 0)
+    assert 'extern "C" __global__' in src and "qsv_pass_jit" in src
+    # an X on a local qubit: both rows are single unit entries -> moves only
+    px = qsv.qsv_plan_create(n, qsv.QSV_C128, [W.gate("X", [11])], mode=qsv.PLAN_PASSES)
+    sx = qsv.qsv_plan_op_source(px, 0)
+    moves = [l for l in sx.splitlines() if "v[" in l and ".x =" in l]
+    assert moves and all("*" not in l for l in moves)
+    # the interpreted plan of the same circuit is left without compiled passes
+    assert qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_PASSES).stats()["n_jit_passes"] == 0

@@ -1,0 +1,130 @@
+"""Compiled LDS passes (plan option jit=1): parity against the oracle and
+against the interpreted pass kernel, through the C ABI."""
+import numpy as np
+import pytest
+
+import paper_2203_08826_amd as qsv
+import workloads as W
+from oracle import statevec as S
+
+pytestmark = pytest.mark.gpu
+
+TOL = {qsv.QSV_C64: 1e-5, qsv.QSV_C128: 1e-12}
+
+
+def _run(psi0, circ, dt, **kw):
+    import torch
+    n = int(psi0.size).bit_length() - 1
+    t = torch.complex64 if dt == qsv.QSV_C64 else torch.complex128
+    st = torch.from_numpy(psi0).to(t).cuda()
+    plan = qsv.qsv_plan_create(n, dt, circ, **kw)
+    qsv.qsv_plan_execute(plan, st)
+    torch.cuda.synchronize()
+    return st.cpu().numpy().astype(np.complex128), plan.stats()
+
+
+CIRCUITS = {
+    "qft": lambda n: W.qft(n),
+    "supremacy": lambda n: W.supremacy(n, 6, seed=n),
+    "variational": lambda n: W.variational(n, 3, seed=n),
+    "random": lambda n: W.random_circuit(n, 150, seed=n, kmax=2, max_controls=2),
+}
+
+
+@pytest.mark.parametrize("dt", [qsv.QSV_C64, qsv.QSV_C128])
+@pytest.mark.parametrize("name", sorted(CIRCUITS))
+@pytest.mark.parametrize("n", [9, 12, 15, 18])
+def test_jit_passes_match_oracle(gpu, dt, name, n):
+    circ = CIRCUITS[name](n)
+    psi0 = W.random_state(n, 5)
+    want = S.run_circuit(psi0, circ)
+    got, stats = _run(psi0, circ, dt, mode=qsv.PLAN_PASSES, jit=1)
+    if stats["n_passes"]:
+        assert stats["n_jit_passes"] >= 1, stats
+    tol = TOL[dt] * (3 if dt == qsv.QSV_C64 and name == "random" else 1)
+    assert np.max(np.abs(got - want)) <= tol, (name, n, stats)
+    # and the interpreted kernel on the same program
+    ref, _ = _run(psi0, circ, dt, mode=qsv.PLAN_PASSES, jit=0)
+    assert np.max(np.abs(got - ref)) <= 2 * tol
+
+
+@pytest.mark.parametrize("local_bits", [9, 10, 11, 12])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_jit_controls_everywhere(gpu, local_bits, seed):
+    """Controls on register bits, thread bits and non-local bits (the chunk
+    shapes move the same qubits between the three), c64 and c128."""
+    n = 16
+    circ = W.random_circuit(n, 200, seed=100 + seed, kmax=2, max_controls=3)
+    psi0 = W.random_state(n, seed)
+    want = S.run_circuit(psi0, circ)
+    for dt in (qsv.QSV_C64, qsv.QSV_C128):
+        if dt == qsv.QSV_C128 and local_bits > 12:
+            continue
+        got, stats = _run(psi0, circ, dt, mode=qsv.PLAN_PASSES, local_bits=local_bits, jit=1)
+        assert stats["n_jit_passes"] >= 1
+        assert np.max(np.abs(got - want)) <= 3 * TOL[dt], (dt, local_bits, stats)
+
+
+@pytest.mark.parametrize("dt", [qsv.QSV_C64, qsv.QSV_C128])
+def test_jit_permutations_are_exact(gpu, dt):
+    """X, CNOT, Toffoli and SWAP only move amplitudes: the compiled kernel
+    turns their rows into register moves, so the result is bit-exact."""
+    n = 15
+    rng = np.random.default_rng(4)
+    circ = []
+    for _ in range(120):
+        kind = int(rng.integers(4))
+        qs = [int(q) for q in rng.choice(n, 3, replace=False)]
+        if kind == 0:
+            circ.append(W.gate("X", qs[:1]))
+        elif kind == 1:
+            circ.append(W.gate("CNOT", qs[:1], qs[1:2]))
+        elif kind == 2:
+            circ.append(W.gate("X", qs[:1], qs[1:3]))
+        else:
+            circ.append(W.gate("SWAP", qs[:2]))
+    psi0 = W.random_state(n, 9)
+    if dt == qsv.QSV_C64:
+        psi0 = psi0.astype(np.complex64).astype(np.complex128)
+    want = S.run_circuit(psi0, circ)
+    got, stats = _run(psi0, circ, dt, mode=qsv.PLAN_PASSES, jit=1)
+    assert stats["n_jit_passes"] >= 1
+    assert np.array_equal(got, want)
+
+
+def test_jit_qft30_sampled_against_closed_form(gpu):
+    """The headline workload in the compiled configuration: 30-qubit QFT,
+    complex64, passes of 12 local bits, 2^16 sampled outputs against the
+    closed form."""
+    import torch
+    n = 30
+    x0 = W.basis_index(n, 0)
+    st = torch.zeros(1 << n, dtype=torch.complex64, device="cuda")
+    st[x0] = 1.0
+    plan = qsv.qsv_plan_create(n, qsv.QSV_C64, W.qft(n), mode=qsv.PLAN_PASSES, local_bits=12, jit=1)
+    assert plan.stats()["n_jit_passes"] >= 1
+    qsv.qsv_plan_execute(plan, st)
+    torch.cuda.synchronize()
+    ys = np.random.default_rng(12).integers(0, 1 << n, size=1 << 16)
+    got = st[torch.from_numpy(ys).cuda()].cpu().numpy().astype(np.complex128)
+    want = S.qft_basis_amplitudes(n, x0, ys)
+    assert np.max(np.abs(got - want)) * 2 ** (n / 2) <= 1e-4
+    assert abs(qsv.qsv_norm2(st).cpu().numpy()[0] - 1.0) <= 1e-5
+
+
+def test_jit_plan_reused_and_repeated(gpu):
+    """A compiled plan executes repeatedly (module loaded once) and two plans
+    with the same passes share the compiled code."""
+    n = 14
+    circ = W.qft(n) + W.supremacy(n, 4, seed=2)
+    psi0 = W.random_state(n, 3)
+    want = S.run_circuit(S.run_circuit(psi0, circ), circ)
+    import torch
+    st = torch.from_numpy(psi0).to(torch.complex128).cuda()
+    p1 = qsv.qsv_plan_create(n, qsv.QSV_C128, circ, mode=qsv.PLAN_PASSES, jit=1)
+    p2 = qsv.qsv_plan_create(n, qsv.QSV_C128, circ, mode=qsv.PLAN_PASSES, jit=1)
+    qsv.qsv_plan_execute(p1, st)
+    del p1
+    qsv.qsv_plan_execute(p2, st)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(st.cpu().numpy() - want)) <= 1e-12
