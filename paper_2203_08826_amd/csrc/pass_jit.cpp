@@ -50,6 +50,34 @@ struct JitModule {
     }
 };
 
+// Enumeration order of the non-local bits (mask ~local over sigma's bits)
+// for chunk-pair work: the lowest K non-local bits, then their images under
+// sigma, then the rest ascending.
+std::vector<int> pair_chunk_order(const std::vector<int> &sigma, uint64_t local) {
+    const int n = (int)sigma.size();
+    constexpr int K = 5;
+    std::vector<int> order, rest;
+    std::vector<int> used(n, 0);
+    int low = 0;
+    for (int b = 0; b < n && low < K; ++b)
+        if (!((local >> b) & 1)) {
+            order.push_back(b);
+            used[b] = 1;
+            ++low;
+        }
+    const size_t nlow = order.size();
+    for (size_t i = 0; i < nlow; ++i) {
+        const int p = sigma[order[i]];
+        if (!used[p]) {
+            order.push_back(p);
+            used[p] = 1;
+        }
+    }
+    for (int b = 0; b < n; ++b)
+        if (!((local >> b) & 1) && !used[b]) order.push_back(b);
+    return order;
+}
+
 namespace {
 
 const char *JIT_KERNEL_NAME = "qsv_pass_jit";
@@ -270,7 +298,8 @@ void Gen::phase(const PassOpDev &op, int sk) {
 
 std::string Gen::source() {
     const int L = P.L, RB = P.RB;
-    const bool PF = f32 ? RB <= 4 : RB <= 3;
+    const bool pair = !P.pair_sigma.empty();
+    const bool PF = !pair && (f32 ? RB <= 4 : RB <= 3);
     bool any_exchange = false;
     for (auto &op : P.ops)
         if (op.kind == POP_EXCHANGE) any_exchange = true;
@@ -351,18 +380,37 @@ std::string Gen::source() {
     for (int j = 0; j < NR; ++j) ld += fmt(" dst[%d] = p[%s];", j, u64(reg_off(P.parts[P.load_part], in_pos, j)).c_str());
     ld += " };";
     ln(ld);
-    ln(fmt("    C v[%d];", NR));
-    ln("    unsigned long long c = blockIdx.x;");
-    if (PF) ln("    if (c < nchunks) load_chunk(v, chunk_base(c));");
-    ln("    for (; c < nchunks; c += gridDim.x) {");
-    ln("        const unsigned long long base = chunk_base(c);");
-    if (PF) {
-        ln(fmt("        C vn[%d];", NR));
-        ln("        const unsigned long long cn = c + gridDim.x;");
-        ln("        if (cn < nchunks) load_chunk(vn, chunk_base(cn));");
-    } else {
-        ln("        load_chunk(v, base);");
+    std::string sto = "    auto store_chunk = [&](const C *src, unsigned long long b) { C *p = psi + (b | lt_out);";
+    for (int j = 0; j < NR; ++j)
+        sto += fmt(" p[%s] = src[%d];", u64(reg_off(P.parts[final_part], out_pos, j)).c_str(), j);
+    sto += " };";
+    ln(sto);
+    if (pair) {
+        // the chunk holding the images of chunk `b` under sigma (non-local bits only)
+        const int n = (int)P.pair_sigma.size();
+        uint64_t local = 0, fixed = 0;
+        for (int l = 0; l < L; ++l) local |= 1ull << P.local_sorted[l];
+        // Work item w -> chunk base: the lowest bits of w go to the lowest
+        // non-local bits and to their images under sigma, so the workgroups
+        // running at the same time cover contiguous runs of chunks on both
+        // sides of their pairs.
+        const std::vector<int> order = pair_chunk_order(P.pair_sigma, local);
+        std::string cbw = "    auto pair_base = [&](unsigned long long w) { return 0ull";
+        for (size_t j = 0; j < order.size(); ++j) cbw += fmt(" | (((w >> %zu) & 1ull) << %d)", j, order[j]);
+        cbw += "; };";
+        ln(cbw);
+        std::string e = "    auto partner = [&](unsigned long long b) { return (b & ";
+        for (int q = 0; q < n; ++q)
+            if (!((local >> q) & 1) && P.pair_sigma[q] == q) fixed |= 1ull << q;
+        e += u64(fixed) + ")";
+        for (int q = 0; q < n; ++q)
+            if (!((local >> q) & 1) && P.pair_sigma[q] != q)
+                e += fmt(" | (((b >> %d) & 1ull) << %d)", q, P.pair_sigma[q]);
+        e += "; };";
+        ln(e);
     }
+    // the ops, once per tile
+    ln("    auto run_ops = [&](C *v, const unsigned long long base) __attribute__((always_inline)) {");
     cur = P.load_part;
     for (size_t o = 0; o < P.ops.size(); ++o) {
         const PassOpDev &op = P.ops[o];
@@ -410,11 +458,41 @@ std::string Gen::source() {
         default: break;
         }
     }
+    ln("    };");
+    ln(fmt("    C v[%d];", NR));
+    ln("    unsigned long long c = blockIdx.x;");
+    if (PF) ln("    if (c < nchunks) load_chunk(v, chunk_base(c));");
+    ln("    for (; c < nchunks; c += gridDim.x) {");
+    ln(pair ? "        const unsigned long long base = pair_base(c);" : "        const unsigned long long base = chunk_base(c);");
+    if (pair) {
+        // chunk pairs (c, sigma(c)), moved by the workgroup of the smaller base;
+        // every load of both tiles completes before the first store (in place)
+        ln("        const unsigned long long pbase = partner(base);");
+        ln("        if (pbase < base) continue;");
+        ln("        const bool pr = pbase != base;");
+        ln(fmt("        C w[%d];", NR));
+        ln("        load_chunk(v, base);");
+        ln("        if (pr) load_chunk(w, pbase);");
+        ln("        run_ops(v, base);");
+        ln("        if (pr) run_ops(w, pbase);");
+        ln("        __builtin_amdgcn_s_waitcnt(0);");
+        ln("        __syncthreads();");
+        ln("        store_chunk(v, pbase);");
+        ln("        if (pr) store_chunk(w, base);");
+        ln("    }");
+        ln("}");
+        return s;
+    }
+    if (PF) {
+        ln(fmt("        C vn[%d];", NR));
+        ln("        const unsigned long long cn = c + gridDim.x;");
+        ln("        if (cn < nchunks) load_chunk(vn, chunk_base(cn));");
+    } else {
+        ln("        load_chunk(v, base);");
+    }
+    ln("        run_ops(v, base);");
     if (relabel) ln("        __syncthreads();");
-    std::string st = "        { C *p = psi + (base | lt_out);";
-    for (int j = 0; j < NR; ++j) st += fmt(" p[%s] = v[%d];", u64(reg_off(P.parts[final_part], out_pos, j)).c_str(), j);
-    st += " }";
-    ln(st);
+    ln("        store_chunk(v, base);");
     if (PF) {
         std::string cp = "       ";
         for (int j = 0; j < NR; ++j) cp += fmt(" v[%d] = vn[%d];", j, j);

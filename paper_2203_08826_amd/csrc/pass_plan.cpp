@@ -137,8 +137,28 @@ Part make_part(int L, int RB, const std::vector<int> &want, const std::vector<in
     return p;
 }
 
+// Relabel a gate's qubits through the bit permutation sig.
+void relabel_gate(PGate &g, const std::vector<int> &sig) {
+    for (int &q : g.targets) q = sig[q];
+    for (int &q : g.controls) q = sig[q];
+    for (auto &t : g.terms) {
+        uint64_t m = 0;
+        for (int b = 0; b < (int)sig.size(); ++b)
+            if ((t.first >> b) & 1) m |= 1ull << sig[b];
+        t.first = m;
+    }
+}
+void relabel_gate(qsv_gate &g, const std::vector<int> &sig) {
+    for (int j = 0; j < g.k; ++j) g.targets[j] = sig[g.targets[j]];
+    for (int j = 0; j < g.c; ++j) g.controls[j] = sig[g.controls[j]];
+}
+
+// `fold` (optional): an involution of the global bits, closed on the local
+// set, applied to the result on store (out[fold(i)] = in[i]): its local part
+// joins the store's bit map and its non-local part pairs chunk c with chunk
+// fold(c), which only the compiled kernel executes.
 int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> &local, int RB,
-                 PassProgram &prog) {
+                 PassProgram &prog, const std::vector<int> *fold = nullptr) {
     const int L = (int)local.size();
     prog.L = L;
     prog.RB = RB;
@@ -213,6 +233,11 @@ int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> 
     prog.out_pos.assign(L, -1);
     for (int q = 0; q < n; ++q)
         if (cur_l[q] >= 0) prog.out_pos[cur_l[q]] = q;
+    prog.pair_sigma.clear();
+    if (fold) {
+        for (int l = 0; l < L; ++l) prog.out_pos[l] = (*fold)[prog.out_pos[l]];
+        prog.pair_sigma = *fold;
+    }
 
     // rank orders: local positions by global bit at load / at store
     std::vector<int> in_rank(L), out_rank(L);
@@ -473,7 +498,9 @@ int pass_register_bits(int n, int dtype, int local_bits) {
     return RB;
 }
 
-int build_passes(qsv_plan *p, int local_bits) {
+namespace {
+
+int build_passes_once(qsv_plan *p, int local_bits, bool allow_fold) {
     const int n = p->n;
     const int RB = pass_register_bits(n, p->dtype, local_bits);
     if (local_bits > 0 && RB < 0) return fail(QSV_ERR_ARG, "local_bits outside the supported range");
@@ -510,21 +537,57 @@ int build_passes(qsv_plan *p, int local_bits) {
         // a two-qubit gate needs two register bits
         if (pgs[i].kind == PGate::NONDIAG && pgs[i].targets.size() > (size_t)RB) pgs[i].kind = PGate::OTHER;
     }
+    // The relabelling left at the end (data of logical qubit q sits at bit
+    // phys[q]) is undone by sigma.  With compiled passes an involution is
+    // folded into the first pass whose local set can be closed under it: that
+    // pass stores its result permuted (P_sigma V_1), and every later gate is
+    // relabelled through sigma, since P_sigma V_2 V_1 = (P_sigma V_2
+    // P_sigma^-1) P_sigma V_1.  Otherwise a bit-permutation kernel (or SWAPs)
+    // runs at the end.
+    std::vector<int> sigma(n);
+    bool moved = false;
+    for (int q = 0; q < n; ++q) {
+        sigma[phys[q]] = q;
+        if (phys[q] != q) moved = true;
+    }
+    bool involution = true;
+    for (int b = 0; b < n; ++b)
+        if (sigma[sigma[b]] != b) involution = false;
+    bool folded = false;
     std::vector<PGate> run;
     uint64_t S = 0;   // local set (global bits) of the open pass
     auto reset_local = [&]() {
         S = 0;
         for (int q = 0; q < lanes; ++q) S |= 1ull << q;
     };
+    // local set of exactly L bits that contains S and is closed under sigma, if any
+    auto close_under_sigma = [&](uint64_t s, uint64_t &out) {
+        for (int b = 0; b < n; ++b)
+            if ((s >> b) & 1) s |= 1ull << sigma[b];
+        for (int b = 0; b < n && __builtin_popcountll(s) < L; ++b)   // fixed points first
+            if (sigma[b] == b) s |= 1ull << b;
+        for (int b = 0; b < n && __builtin_popcountll(s) + 1 < L; ++b)
+            if (!((s >> b) & 1)) s |= (1ull << b) | (1ull << sigma[b]);
+        if (__builtin_popcountll(s) != L) return false;
+        out = s;
+        return true;
+    };
     auto close = [&]() -> int {
         if (run.empty()) return QSV_OK;
+        const std::vector<int> *fold = nullptr;
+        uint64_t Sc = 0;
+        if (!folded && allow_fold && moved && involution && close_under_sigma(S, Sc)) {
+            S = Sc;
+            fold = &sigma;
+            folded = true;
+        }
         // fill the local set with the lowest missing bits
         for (int q = 0; q < n && __builtin_popcountll(S) < L; ++q) S |= 1ull << q;
         std::vector<int> local;
         for (int q = 0; q < n; ++q)
             if ((S >> q) & 1) local.push_back(q);
         auto prog = std::make_shared<PassProgram>();
-        int st = compile_pass(n, run, local, RB, *prog);
+        int st = compile_pass(n, run, local, RB, *prog, fold);
         if (st) return st;
         PlanOp op;
         op.kind = PlanOp::PASS;
@@ -542,37 +605,41 @@ int build_passes(qsv_plan *p, int local_bits) {
         return QSV_OK;
     };
     reset_local();
+    bool relabelled = false;   // gates from here on are relabelled through sigma
+    auto sync_relabel = [&](size_t from) {
+        if (!folded || relabelled) return;
+        relabelled = true;
+        for (size_t k = from; k < pgs.size(); ++k) {
+            relabel_gate(pgs[k], sigma);
+            relabel_gate(gates[k], sigma);
+        }
+    };
     for (size_t i = 0; i < pgs.size(); ++i) {
         PGate &g = pgs[i];
         if (g.kind == PGate::OTHER) {
             int st = close();
+            sync_relabel(i);
             if (!st) st = plan_add_gate_op(p, gates[i]);
             if (st) return st;
             continue;
         }
-        uint64_t need = 0;
-        if (g.kind == PGate::NONDIAG || g.kind == PGate::SWAP)
-            for (int q : g.targets) need |= 1ull << q;
-        if (__builtin_popcountll(S | need) > L) {
+        auto needed = [&]() {
+            uint64_t m = 0;
+            if (g.kind == PGate::NONDIAG || g.kind == PGate::SWAP)
+                for (int q : g.targets) m |= 1ull << q;
+            return m;
+        };
+        if (__builtin_popcountll(S | needed()) > L) {
             int st = close();
             if (st) return st;
+            sync_relabel(i);
         }
-        S |= need;
+        S |= needed();
         run.push_back(g);
     }
     int st = close();
     if (st) return st;
-    // undo the relabelling: data of logical qubit q sits at bit phys[q]
-    std::vector<int> sigma(n);
-    bool moved = false;
-    for (int q = 0; q < n; ++q) {
-        sigma[phys[q]] = q;
-        if (phys[q] != q) moved = true;
-    }
-    if (!moved) return QSV_OK;
-    bool involution = true;
-    for (int b = 0; b < n; ++b)
-        if (sigma[sigma[b]] != b) involution = false;
+    if (!moved || folded) return QSV_OK;
     const double s_amp = p->dtype == QSV_C64 ? 8.0 : 16.0;
     if (involution) {
         PlanOp op;
@@ -600,6 +667,35 @@ int build_passes(qsv_plan *p, int local_bits) {
         std::swap(at[b], at[other]);
         phys[qb] = other;
         phys[b] = b;
+    }
+    return QSV_OK;
+}
+
+}  // namespace
+
+// With compiled passes, the plan that folds the final permutation into a pass
+// (see above) is kept only when it needs fewer sweeps over the state than
+// the plan that ends with a bit-permutation kernel: a chunk-pair pass costs
+// more than a plain pass.
+int build_passes(qsv_plan *p, int local_bits) {
+    if (!p->opts.jit) return build_passes_once(p, local_bits, false);
+    const size_t ops0 = p->ops.size();
+    const qsv_plan_stats st0 = p->stats;
+    int st = build_passes_once(p, local_bits, true);
+    if (st) return st;
+    bool paired = false;
+    for (size_t i = ops0; i < p->ops.size(); ++i)
+        if (p->ops[i].kind == PlanOp::PASS && !p->ops[i].pass->pair_sigma.empty()) paired = true;
+    if (!paired) return QSV_OK;
+    std::vector<PlanOp> fold_ops(p->ops.begin() + ops0, p->ops.end());
+    const qsv_plan_stats fold_stats = p->stats;
+    p->ops.resize(ops0);
+    p->stats = st0;
+    if ((st = build_passes_once(p, local_bits, false))) return st;
+    if (fold_ops.size() < p->ops.size() - ops0) {
+        p->ops.resize(ops0);
+        p->ops.insert(p->ops.end(), fold_ops.begin(), fold_ops.end());
+        p->stats = fold_stats;
     }
     return QSV_OK;
 }

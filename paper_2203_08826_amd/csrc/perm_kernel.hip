@@ -7,7 +7,8 @@
 // one read + write of the state.  A chunk's local bits are closed under
 // sigma and include the lowest bits, so both the loads and the stores are
 // contiguous runs; sigma maps chunk c to chunk sigma(c), and one workgroup
-// moves the pair (c, sigma(c)) through LDS, which keeps the update in place.
+// moves the pair (c, sigma(c)) through LDS, one chunk at a time, after both
+// are in registers, which keeps the update in place.
 #include "plan_internal.h"
 
 namespace qsv {
@@ -16,10 +17,10 @@ constexpr int BP_THREADS = 256;
 constexpr int BP_MAX_L = 12;
 
 struct BitPermArgs {
-    uint64_t lowmask[BP_MAX_L];    // sorted local bits, for the chunk base
     int32_t lpos[BP_MAX_L];        // global bit of local position l
     int32_t lperm[BP_MAX_L];       // local position l -> local position of sigma(bit)
     int32_t gperm[QSV_MAX_QUBITS]; // global bit b -> sigma(b)
+    int32_t order[QSV_MAX_QUBITS]; // work-item bit j -> non-local global bit
     int32_t L;
     int32_t n;
     uint64_t nchunks;
@@ -34,14 +35,22 @@ __device__ __forceinline__ uint64_t bp_permute_global(uint64_t x, const BitPermA
     return y;
 }
 
-template <typename C>
-__global__ void __launch_bounds__(BP_THREADS) k_bitperm(C *__restrict__ psi, BitPermArgs a) {
-    __shared__ C buf[2][1 << (BP_MAX_L - (sizeof(C) == 16 ? 1 : 0))];
+// An amplitude as a plain pair (HIP's vector types keep register arrays of
+// them out of registers here).  Same layout as float2 / double2.
+template <typename R> struct alignas(2 * sizeof(R)) BpC {
+    R x, y;
+};
+
+template <typename R>
+__global__ void __launch_bounds__(BP_THREADS) k_bitperm(BpC<R> *__restrict__ psi, BitPermArgs a) {
+    typedef BpC<R> C;
+    constexpr int LMAX = BP_MAX_L - (sizeof(C) == 16 ? 1 : 0);
+    constexpr int IT = (1 << LMAX) / BP_THREADS;   // elements per thread of the largest chunk
+    __shared__ C buf[1 << LMAX];
     // scatter tables: local index l = (hi << 6) | lo -> global offset, and the
     // local permutation, split in 6-bit halves
     __shared__ uint64_t sc_lo[64], sc_hi[64];
     __shared__ uint32_t lm_lo[64], lm_hi[64];
-    const uint64_t c = blockIdx.x;
     const int L = a.L;
     const uint32_t csize = 1u << L;
     if (threadIdx.x < 64) {
@@ -66,62 +75,82 @@ __global__ void __launch_bounds__(BP_THREADS) k_bitperm(C *__restrict__ psi, Bit
         lm_hi[x] = mhi;
     }
     __syncthreads();
-    if (c >= a.nchunks) return;
-    // chunk base from the chunk index, then its partner under sigma
-    uint64_t base = c;
-    for (int b = 0; b < L; ++b) {
-        const uint64_t lo = base & a.lowmask[b];
-        base = lo | ((base ^ lo) << 1);
-    }
-    const uint64_t pbase = bp_permute_global(base, a);   // non-local bits only (local set is closed)
-    // partner chunk index: squeeze out the local bits of pbase
-    uint64_t pc = 0;
-    {
-        int k = 0, li = 0;
-        for (int b = 0; b < a.n; ++b) {
-            if (li < L && a.lpos[li] == b) {
-                ++li;
-                continue;
+    // Persistent workgroups walk the work items; item w is the chunk whose
+    // non-local bits are w's bits in the order a.order (the lowest non-local
+    // bits and their images under sigma vary fastest, so the workgroups
+    // running at the same time read contiguous runs on both sides of their
+    // pairs).  The workgroup of the smaller base of a pair moves both.
+    const int nn = a.n - L;
+    for (uint64_t w = blockIdx.x; w < a.nchunks; w += gridDim.x) {
+        uint64_t base = 0;
+        for (int j = 0; j < nn; ++j) base |= ((w >> j) & 1ull) << a.order[j];
+        const uint64_t pbase = bp_permute_global(base, a);   // non-local bits only (local set is closed)
+        if (pbase < base) continue;   // uniform: the partner's iteration moves this pair
+        const bool pair = pbase != base;
+        // Both chunks are loaded before anything is stored; each thread writes
+        // its loaded values to LDS before the barrier that precedes the first
+        // store, so every load of the pair has completed by then (in place).
+        // (real and imaginary parts in arrays of their own, which stay in registers)
+        R r0x[IT], r0y[IT], r1x[IT], r1y[IT];
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const uint32_t l = threadIdx.x + i * BP_THREADS;
+            if (l < csize) {
+                const uint64_t off = sc_lo[l & 63] | sc_hi[l >> 6];
+                const C x = psi[base | off];
+                r0x[i] = x.x;
+                r0y[i] = x.y;
+                if (pair) {
+                    const C y = psi[pbase | off];
+                    r1x[i] = y.x;
+                    r1y[i] = y.y;
+                }
             }
-            if ((pbase >> b) & 1) pc |= 1ull << k;
-            ++k;
         }
-    }
-    if (pc < c) return;   // the partner's workgroup moves this pair
-    const bool pair = pc != c;
-    // fixed trip count (the largest chunk) so that all loads are issued
-    // before the first LDS store
-    constexpr int IT = (1 << (BP_MAX_L - (sizeof(C) == 16 ? 1 : 0))) / BP_THREADS;
-    C r0[IT], r1[IT];
+        // element l of chunk c lands at local position lmap(l) of chunk sigma(c):
+        // every output position lo reads its source lmap(lo) (sigma is an involution)
+        __syncthreads();   // the previous pair's LDS reads are done
 #pragma unroll
-    for (int i = 0; i < IT; ++i) {
-        const uint32_t l = threadIdx.x + i * BP_THREADS;
-        if (l < csize) {
-            const uint64_t off = sc_lo[l & 63] | sc_hi[l >> 6];
-            r0[i] = psi[base | off];
-            if (pair) r1[i] = psi[pbase | off];
+        for (int i = 0; i < IT; ++i) {
+            const uint32_t l = threadIdx.x + i * BP_THREADS;
+            if (l < csize) buf[bp_swz(l)] = C{r0x[i], r0y[i]};
         }
-    }
+        __syncthreads();
 #pragma unroll
-    for (int i = 0; i < IT; ++i) {
-        const uint32_t l = threadIdx.x + i * BP_THREADS;
-        if (l < csize) {
-            buf[0][bp_swz(l)] = r0[i];
-            if (pair) buf[1][bp_swz(l)] = r1[i];
+        for (int i = 0; i < IT; ++i) {
+            const uint32_t lo = threadIdx.x + i * BP_THREADS;
+            if (lo < csize) {
+                const C x = buf[bp_swz(lm_lo[lo & 63] | lm_hi[lo >> 6])];
+                r0x[i] = x.x;
+                r0y[i] = x.y;
+            }
         }
-    }
-    __syncthreads();
-    // element l of chunk c lands at local position lmap(l) of chunk sigma(c):
-    // write every output position in order, reading its source (sigma is an
-    // involution, so the source of lo is lmap(lo))
+        if (pair) {
+            __syncthreads();
 #pragma unroll
-    for (int i = 0; i < IT; ++i) {
-        const uint32_t lo = threadIdx.x + i * BP_THREADS;
-        if (lo < csize) {
-            const uint64_t off = sc_lo[lo & 63] | sc_hi[lo >> 6];
-            const uint32_t li = lm_lo[lo & 63] | lm_hi[lo >> 6];
-            psi[pbase | off] = buf[0][bp_swz(li)];
-            if (pair) psi[base | off] = buf[1][bp_swz(li)];
+            for (int i = 0; i < IT; ++i) {
+                const uint32_t l = threadIdx.x + i * BP_THREADS;
+                if (l < csize) buf[bp_swz(l)] = C{r1x[i], r1y[i]};
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < IT; ++i) {
+                const uint32_t lo = threadIdx.x + i * BP_THREADS;
+                if (lo < csize) {
+                    const C x = buf[bp_swz(lm_lo[lo & 63] | lm_hi[lo >> 6])];
+                    r1x[i] = x.x;
+                    r1y[i] = x.y;
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const uint32_t lo = threadIdx.x + i * BP_THREADS;
+            if (lo < csize) {
+                const uint64_t off = sc_lo[lo & 63] | sc_hi[lo >> 6];
+                psi[pbase | off] = C{r0x[i], r0y[i]};
+                if (pair) psi[base | off] = C{r1x[i], r1y[i]};
+            }
         }
     }
 }
@@ -152,22 +181,41 @@ int launch_bitperm(void *state, int n, int dtype, const std::vector<int> &sigma,
     for (int b = 0; b < n; ++b)
         if (in_set[b]) {
             a.lpos[L] = b;
-            a.lowmask[L] = (1ull << b) - 1ull;
             ++L;
         }
     a.L = L;
     for (int b = 0; b < n; ++b) a.gperm[b] = sigma[b];
+    {
+        uint64_t lm = 0;
+        for (int i = 0; i < L; ++i) lm |= 1ull << a.lpos[i];
+        const std::vector<int> order = pair_chunk_order(sigma, lm);
+        for (size_t j = 0; j < order.size(); ++j) a.order[j] = order[j];
+    }
     for (int i = 0; i < L; ++i) {
         const int dst = sigma[a.lpos[i]];
         for (int k = 0; k < L; ++k)
             if (a.lpos[k] == dst) a.lperm[i] = k;
     }
     a.nchunks = 1ull << (n - L);
-    const unsigned grid = (unsigned)a.nchunks;
+    // persistent grid: as many workgroups as can be resident
+    static int resident[2][64] = {{0}};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev < 0 || dev >= 64) dev = 0;
+    const int di = dtype == QSV_C64 ? 0 : 1;
+    if (resident[di][dev] == 0) {
+        int per_cu = 0;
+        hipError_t e = dtype == QSV_C64
+                           ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bitperm<float>, BP_THREADS, 0)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bitperm<double>, BP_THREADS, 0);
+        if (e != hipSuccess || per_cu < 1) per_cu = 1;
+        resident[di][dev] = per_cu;
+    }
+    const unsigned grid = (unsigned)std::min<uint64_t>(a.nchunks, (uint64_t)resident[di][dev] * device_sm_count());
     if (dtype == QSV_C64)
-        hipLaunchKernelGGL(k_bitperm<float2>, dim3(grid), dim3(BP_THREADS), 0, s, (float2 *)state, a);
+        hipLaunchKernelGGL(k_bitperm<float>, dim3(grid), dim3(BP_THREADS), 0, s, (BpC<float> *)state, a);
     else
-        hipLaunchKernelGGL(k_bitperm<double2>, dim3(grid), dim3(BP_THREADS), 0, s, (double2 *)state, a);
+        hipLaunchKernelGGL(k_bitperm<double>, dim3(grid), dim3(BP_THREADS), 0, s, (BpC<double> *)state, a);
     QSV_HIP_CHECK(hipGetLastError());
     return QSV_OK;
 }

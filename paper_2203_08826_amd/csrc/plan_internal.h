@@ -109,6 +109,7 @@ struct PassProgram {
     int n_gates = 0;                      // circuit gates folded into this pass
     std::vector<uint8_t> blob;            // serialised program
     std::shared_ptr<JitModule> jit;       // compiled kernel, when the plan asked for one
+    std::vector<int> pair_sigma;          // if set: chunk c is stored at chunk pair_sigma(c) (compiled kernel only)
     void serialise();
 };
 
@@ -116,6 +117,7 @@ int upload_pass_program(const PassProgram &prog, int dtype, hipStream_t s, Stagi
 int launch_pass_program(void *state, int n, int dtype, const PassProgram &prog, hipStream_t s);
 int launch_pass_jit(void *state, int n, int dtype, const PassProgram &prog, hipStream_t s);
 std::string pass_jit_source(const PassProgram &prog, int dtype);
+std::vector<int> pair_chunk_order(const std::vector<int> &sigma, uint64_t local);
 int launch_bitperm(void *state, int n, int dtype, const std::vector<int> &sigma, hipStream_t s);
 
 // ---------------------------------------------------------------- plans

@@ -116,3 +116,14 @@ def test_pass_compilation_on_host():
     assert moves and all("*" not in l for l in moves)
     # the interpreted plan of the same circuit is left without compiled passes
     assert qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_PASSES).stats()["n_jit_passes"] == 0
+
+
+def test_final_permutation_folds_only_when_it_saves_a_sweep():
+    n = 20
+    circ = [W.gate("H", [q]) for q in range(4)] + [W.gate("SWAP", [i, n - 1 - i]) for i in range(n // 2)]
+    kinds = lambda p: [qsv.qsv_plan_op_info(p, i)["kind"] for i in range(p.stats()["n_launches"])]
+    assert kinds(qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_PASSES, local_bits=12)) == [2, 3]
+    assert kinds(qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_PASSES, local_bits=12, jit=1)) == [2]
+    # the 30-qubit QFT would need one more pass to fold its reversal: kept as a permutation sweep
+    q = qsv.qsv_plan_create(30, qsv.QSV_C64, W.qft(30), mode=qsv.PLAN_PASSES, local_bits=12, jit=1)
+    assert kinds(q)[-1] == 3 and len(kinds(q)) == 5

@@ -128,3 +128,36 @@ def test_jit_plan_reused_and_repeated(gpu):
     qsv.qsv_plan_execute(p2, st)
     torch.cuda.synchronize()
     assert np.max(np.abs(st.cpu().numpy() - want)) <= 1e-12
+
+
+def _fold_circuit(n):
+    circ = [W.gate("H", [q]) for q in range(3)]
+    circ += [W.gate("CU1", [q + 1], [q], [0.3 * (q + 1)]) for q in range(3)]
+    circ += [W.gate("X", [1], [0, 2])]
+    return circ + [W.gate("SWAP", [i, n - 1 - i]) for i in range(n // 2)]
+
+
+@pytest.mark.parametrize("dt", [qsv.QSV_C64, qsv.QSV_C128])
+@pytest.mark.parametrize("n", [13, 16, 19])
+def test_jit_permutation_folded_into_a_pass(gpu, dt, n):
+    """The final qubit reversal is stored by the pass itself (chunk pairs
+    (c, sigma(c)) moved by one workgroup, in place): no permutation kernel."""
+    circ = _fold_circuit(n)
+    psi0 = W.random_state(n, 1)
+    want = S.run_circuit(psi0, circ)
+    got, stats = _run(psi0, circ, dt, mode=qsv.PLAN_PASSES, local_bits=12, jit=1)
+    assert stats["n_launches"] == stats["n_jit_passes"] == 1, stats
+    assert np.max(np.abs(got - want)) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", [qsv.QSV_C64, qsv.QSV_C128])
+def test_jit_folded_pure_permutation_is_exact(gpu, dt):
+    n = 18
+    circ = [W.gate("X", [0]), W.gate("CNOT", [2], [1])] + [W.gate("SWAP", [i, n - 1 - i]) for i in range(n // 2)]
+    psi0 = W.random_state(n, 2)
+    if dt == qsv.QSV_C64:
+        psi0 = psi0.astype(np.complex64).astype(np.complex128)
+    want = S.run_circuit(psi0, circ)
+    got, stats = _run(psi0, circ, dt, mode=qsv.PLAN_PASSES, local_bits=12, jit=1)
+    assert stats["n_launches"] == 1, stats
+    assert np.array_equal(got, want)
