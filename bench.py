@@ -3,8 +3,9 @@
 A step is one application of the whole QFT circuit (n H gates, n(n-1)/2
 controlled phases, n/2 SWAPs) to a 2^n complex64 state resident in HBM,
 with the plan the library picks (LDS passes scored by the cost model when
-one is loaded).  Also reported: the same circuit as plain per-gate
-complex128 and per-gate / greedy-fused complex64, the complex64 state's
+one is loaded; passes compiled into kernels of their own unless --jit 0).
+Also reported: the same circuit as plain per-gate complex128, per-gate /
+greedy-fused complex64 and interpreted LDS passes, the complex64 state's
 infidelity against the complex128 one, a closed-form check of sampled
 amplitudes, the roofline of the dominant kernel and the oracle timed on the
 host cores.
@@ -33,6 +34,7 @@ def parse():
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--plan", default="learned", choices=["per_gate", "greedy", "passes", "learned"])
     ap.add_argument("--kmax", type=int, default=2)
+    ap.add_argument("--jit", type=int, default=1, choices=[0, 1], help="compile the LDS passes (1) or interpret them (0)")
     ap.add_argument("--no-baselines", action="store_true", help="skip the per-gate / c128 comparison plans")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-gates", type=int, default=4, help="oracle sample: first gates of the circuit")
@@ -87,8 +89,9 @@ def workload_supremacy(args):
     out = {"metric": "circuit s & HBM GB/s", "config": {"workload": "supremacy-like n=%d depth=%d (%d gates)" % (
         n, args.depth, len(circ))}, "results": {}}
     for dname, dt, tdt in (("c64", qsv.QSV_C64, torch.complex64), ("c128", qsv.QSV_C128, torch.complex128)):
-        for pname, mode in (("per_gate", qsv.PLAN_PER_GATE), ("passes", qsv.PLAN_PASSES)):
-            plan = qsv.qsv_plan_create(n, dt, circ, mode=mode)
+        for pname, mode, jit in (("per_gate", qsv.PLAN_PER_GATE, 0), ("passes", qsv.PLAN_PASSES, 0),
+                                 ("passes_compiled", qsv.PLAN_PASSES, 1)):
+            plan = qsv.qsv_plan_create(n, dt, circ, mode=mode, jit=jit)
             st = _zero_state(n, tdt)
             s = _timed(lambda: qsv.qsv_plan_execute(plan, st), 1)
             b = plan.stats()["bytes"]
@@ -190,7 +193,8 @@ def workload_learned(args):
     for name, circ in (("qft", W.qft(n)), ("supremacy_d30", W.supremacy(n, 30, seed=1))):
         row = {}
         states = {}
-        for pname, kw in (("learned", dict(mode=qsv.PLAN_LEARNED, kmax=2)), ("greedy2", dict(mode=qsv.PLAN_GREEDY, kmax=2)),
+        for pname, kw in (("learned", dict(mode=qsv.PLAN_LEARNED, kmax=2, jit=args.jit)),
+                          ("greedy2", dict(mode=qsv.PLAN_GREEDY, kmax=2)),
                           ("unfused", dict(mode=qsv.PLAN_PER_GATE))):
             plan = qsv.qsv_plan_create(n, qsv.QSV_C64, circ, **kw)
             st = _zero_state(n, torch.complex64)
@@ -313,7 +317,9 @@ def main():
 
     # ---------------------------------------------------------- headline plan
     dt = qsv.QSV_C64
-    plan = qsv.qsv_plan_create(n, dt, circ, mode=modes[args.plan], kmax=args.kmax)
+    t_create = time.perf_counter()
+    plan = qsv.qsv_plan_create(n, dt, circ, mode=modes[args.plan], kmax=args.kmax, jit=args.jit)
+    create_s = time.perf_counter() - t_create
     pstats = plan.stats()
     st = basis(torch.complex64)
     # correctness spot check on one fresh application: closed form of QFT|x0>
@@ -350,7 +356,8 @@ def main():
         k["count"] += 1
         k["bytes"] += info["bytes"]
         k["flops"] += info["flops"]
-    kind_names = {0: "gate", 1: "mfma_block", 2: "lds_pass"}
+    kind_names = {0: "gate", 1: "mfma_block", 2: "lds_pass_compiled" if pstats["n_jit_passes"] else "lds_pass",
+                  3: "bit_permutation"}
     dom = max(per_kind, key=lambda k: per_kind[k]["time"])
     d = per_kind[dom]
     avg_dur = d["time"] / d["count"]
@@ -369,7 +376,8 @@ def main():
         torch.cuda.empty_cache()
         for name, mode, cdt, tdt, steps in (("plain_c128", qsv.PLAN_PER_GATE, qsv.QSV_C128, torch.complex128, 2),
                                             ("per_gate_c64", qsv.PLAN_PER_GATE, qsv.QSV_C64, torch.complex64, 2),
-                                            ("greedy2_c64", qsv.PLAN_GREEDY, qsv.QSV_C64, torch.complex64, 2)):
+                                            ("greedy2_c64", qsv.PLAN_GREEDY, qsv.QSV_C64, torch.complex64, 2),
+                                            ("passes_interpreted_c64", qsv.PLAN_PASSES, qsv.QSV_C64, torch.complex64, 3)):
             p2 = qsv.qsv_plan_create(n, cdt, circ, mode=mode, kmax=2)
             s2 = basis(tdt)
             if name == "plain_c128":
@@ -423,7 +431,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "QFT n=%d (%d gates), complex64 state from basis |x0>, x0 seeded" % (n, len(circ)),
                    "plan": args.plan, "plan_used": pstats["mode_used"], "model_loaded": model_loaded,
-                   "launches": pstats["n_launches"], "passes": pstats["n_passes"]},
+                   "launches": pstats["n_launches"], "passes": pstats["n_passes"],
+                   "compiled_passes": pstats["n_jit_passes"]},
+        "plan_create_s": round(create_s, 3),
         "hbm_gbps": round(gbps, 1),
         "hbm_frac": round(gbps / HBM_PEAK_GBS, 4),
         "plan_bytes": bytes_plan,

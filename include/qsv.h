@@ -289,10 +289,12 @@ int qsv_cost_model_set(const float *params, const int *sizes, int nlayers,
                        const float *feat_mean, const float *feat_scale);
 /* Host-only: the raw feature vector (QSV_COST_FEATURES floats) of op `index`
  * of a plan -- n, dtype, one-hot variant (single-gate kernel, fused block on
- * the VALU kernels, MFMA block, LDS pass, bit permutation), number of
- * qubits, number of qubits below 5, log2 bytes, log2 flops, and an
- * op-specific size (log2 touched members, or ops in a pass program). */
-#define QSV_COST_FEATURES 12
+ * the VALU kernels, MFMA block, interpreted LDS pass, bit permutation,
+ * compiled LDS pass -- a pass counts as compiled when the plan was created
+ * with opts->jit), number of qubits, number of qubits below 5, log2 bytes,
+ * log2 flops, and an op-specific size (log2 touched members, or ops in a
+ * pass program). */
+#define QSV_COST_FEATURES 13
 int qsv_plan_op_features(const qsv_plan *plan, int index, float *out);
 
 #ifdef __cplusplus

@@ -8,7 +8,7 @@ LIB_PATH = os.path.join(HERE, "libqsv.so")
 QSV_OK = 0
 QSV_C64, QSV_C128 = 0, 1
 MAX_TARGETS, MAX_CONTROLS = 6, 8
-COST_FEATURES = 12
+COST_FEATURES = 13
 
 PLAN_PER_GATE, PLAN_GREEDY, PLAN_PASSES, PLAN_LEARNED = 0, 1, 2, 3
 

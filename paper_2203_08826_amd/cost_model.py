@@ -27,16 +27,19 @@ SIZES = [COST_FEATURES, 64, 64, 1]
 DEFAULT_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cost_model.npz")
 
 
-def candidate_configs(n, dtype):
-    """The plans the learned planner chooses among (mirrors build_learned)."""
+def candidate_configs(n, dtype, jit=(0, 1)):
+    """The plans the learned planner chooses among (mirrors build_learned),
+    with the LDS passes interpreted and compiled."""
     out = [("per_gate", dict(mode=PLAN_PER_GATE))]
     for k in range(2, 6):
         out.append(("greedy%d" % k, dict(mode=PLAN_GREEDY, kmax=k, use_mfma=1)))
     ld = (5 if dtype == QSV_C64 else 4) + 8
-    if n >= ld:
-        out.append(("passes%d" % ld, dict(mode=PLAN_PASSES, local_bits=ld)))
-    if n >= ld - 1:
-        out.append(("passes%d" % (ld - 1), dict(mode=PLAN_PASSES, local_bits=ld - 1)))
+    for j in jit:
+        sfx = "_jit" if j else ""
+        if n >= ld:
+            out.append(("passes%d%s" % (ld, sfx), dict(mode=PLAN_PASSES, local_bits=ld, jit=j)))
+        if n >= ld - 1:
+            out.append(("passes%d%s" % (ld - 1, sfx), dict(mode=PLAN_PASSES, local_bits=ld - 1, jit=j)))
     return out
 
 

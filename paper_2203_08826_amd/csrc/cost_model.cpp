@@ -5,7 +5,9 @@
 // The model maps the features of one op (qsv_plan_op_features) to the log of
 // its run time; a plan's predicted time is the sum over its ops.  Candidate
 // plans: per-gate, greedy fusion with kmax = 2..5 (matrix-core blocks for
-// complex64), and LDS passes with the default and one smaller chunk.
+// complex64), and LDS passes with the default and one smaller chunk
+// (compiled when the plan asks for compiled passes; only the chosen plan's
+// passes are compiled).
 // Inference runs on the GPU with the library's own MLP kernels.
 #include <cmath>
 #include <cstring>
@@ -50,7 +52,7 @@ void op_features(const qsv_plan *p, const PlanOp &op, float *f) {
         extra = (double)op.qubits.size();
         break;
     case PlanOp::PASS:
-        variant = 3;
+        variant = p->opts.jit ? 5 : 3;
         qubits = op.pass->local_sorted;
         extra = (double)op.pass->ops.size();
         break;
@@ -61,14 +63,14 @@ void op_features(const qsv_plan *p, const PlanOp &op, float *f) {
         break;
     }
     f[2 + variant] = 1.0f;
-    f[7] = (float)qubits.size();
+    f[8] = (float)qubits.size();
     int low = 0;
     for (int q : qubits)
         if (q < 5) ++low;
-    f[8] = (float)low;
-    f[9] = (float)std::log2(std::max(1.0, op.bytes));
-    f[10] = (float)std::log2(1.0 + op.flops);
-    f[11] = (float)extra;
+    f[9] = (float)low;
+    f[10] = (float)std::log2(std::max(1.0, op.bytes));
+    f[11] = (float)std::log2(1.0 + op.flops);
+    f[12] = (float)extra;
 }
 
 // Predicted seconds of every candidate (sum over its ops), on the GPU.
@@ -122,7 +124,7 @@ static std::unique_ptr<qsv_plan> candidate(const qsv_plan *p, int mode, int kmax
     c->n = p->n;
     c->dtype = p->dtype;
     c->gates = p->gates;
-    c->opts = {mode, kmax, local_bits, use_mfma};
+    c->opts = {mode, kmax, local_bits, use_mfma, p->opts.jit};
     std::memset(&c->stats, 0, sizeof(c->stats));
     int st = QSV_OK;
     if (mode == QSV_PLAN_PER_GATE) {

@@ -43,13 +43,14 @@ def test_model_fits_its_training_data(trained):
     assert trained["fit_err"] < 0.5
 
 
+@pytest.mark.parametrize("jit", [0, 1])
 @pytest.mark.parametrize("name", ["qft", "supremacy"])
-def test_learned_beats_greedy_and_matches_unfused(trained, name):
+def test_learned_beats_greedy_and_matches_unfused(trained, name, jit):
     import torch
     n = 24
     circ = W.qft(n) if name == "qft" else W.supremacy(n, 12, seed=9)
     psi0 = W.random_state(n, 3)
-    learned = qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_LEARNED, kmax=2)
+    learned = qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_LEARNED, kmax=2, jit=jit)
     greedy = qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_GREEDY, kmax=2)
     plain = qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_PER_GATE)
     ls = learned.stats()
