@@ -224,10 +224,11 @@ def measured_traffic(kind):
     """HBM bytes per launch of the dominant kernel from the committed
     FETCH_SIZE / WRITE_SIZE summary (scaled by the copy-kernel calibration),
     or None when that summary was taken on a different version of the kernel."""
-    if kind != "lds_pass":
+    files = {"lds_pass": "lds_pass_qft30_c64_traffic.md", "lds_pass_compiled": "lds_pass_compiled_qft30_c64_traffic.md"}
+    if kind not in files:
         return None
     import hashlib
-    path = os.path.join(ROOT, "profiles", "lds_pass_qft30_c64_traffic.md")
+    path = os.path.join(ROOT, "profiles", files[kind])
     if not os.path.exists(path):
         return None
     info = None
