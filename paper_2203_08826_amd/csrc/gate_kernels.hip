@@ -14,10 +14,10 @@
 //             diagonal gates);
 //   k_perm  : M members each replaced by a (phase times) another member
 //             (X/CNOT, Y, SWAP): pure moves are bit-exact;
-//   k_low1  : one-target dense gates on a low qubit; each lane streams a
-//             contiguous 16-byte vector and partners inside the wave are
-//             exchanged with cross-lane shuffles, so every access stays a
-//             full contiguous vector.
+//   k_low1  : one-target dense complex64 gates on a low qubit; each lane
+//             streams a contiguous 16-byte vector and partners inside the
+//             wave are exchanged with cross-lane shuffles, so every access
+//             stays a full contiguous vector.
 #include "qsv_internal.h"
 
 namespace qsv {
@@ -59,12 +59,19 @@ __device__ inline uint64_t group_base(uint64_t g, const GroupArgs &ga) {
     return i | ga.cmask;
 }
 
-// Work per thread per loop iteration: U units of VG consecutive groups.
-// Several independent units keep enough loads in flight to cover HBM latency
-// when a group is small; when bit 0 is not a gate bit, VG = 2 consecutive
-// groups are adjacent in memory and each member access is a 16-byte (c64) or
-// 32-byte (c128) vector.
-template <int M> struct Unroll { static constexpr int U = M <= 2 ? 4 : (M <= 4 ? 2 : 1); };
+// Work per thread: U units of VG consecutive groups.  Several independent
+// units keep enough loads in flight to cover HBM latency when a group is
+// small; when bit 0 is not a gate bit, VG = 2 consecutive groups are adjacent
+// in memory and each member access is a 16-byte (c64) or 32-byte (c128)
+// vector.  A workgroup covers U * 256 consecutive units (unit u of a thread
+// is 256 units after unit u - 1) and the grid covers the state once, so the
+// workgroups resident at any time stream through one contiguous window of
+// memory: on MI355X this sustains ~5.9 TB/s for in-place updates, against
+// ~5.1 TB/s for grid-stride loops whose threads jump a whole grid ahead.
+// Measured on MI355X at 30-33 qubits: four units per thread only pay for
+// complex64 groups of up to two members; everything else streams best with
+// one unit per thread.
+template <typename C, int M> struct Unroll { static constexpr int U = (sizeof(C) == 8 && M <= 2) ? 4 : 1; };
 
 template <int U, int VG>
 __device__ __forceinline__ void unit_bases(uint64_t w0, uint64_t wstride, uint64_t nunits, const GroupArgs &ga,
@@ -79,14 +86,14 @@ __device__ __forceinline__ void unit_bases(uint64_t w0, uint64_t wstride, uint64
 
 template <typename C, int M, int VG>
 __global__ void __launch_bounds__(256) k_dense(C *__restrict__ psi, GroupArgs ga, DenseArgs<C, M> da) {
-    constexpr int U = Unroll<M>::U;
+    constexpr int U = Unroll<C, M>::U;
     const uint64_t nunits = ga.ngroups / VG;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t w0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w0 < nunits; w0 += U * stride) {
+    const uint64_t span = (uint64_t)U * blockDim.x;
+    for (uint64_t w0 = (uint64_t)blockIdx.x * span + threadIdx.x; w0 < nunits; w0 += (uint64_t)gridDim.x * span) {
         uint64_t base[U];
         bool live[U];
         C v[U][M][VG];
-        unit_bases<U, VG>(w0, stride, nunits, ga, base, live);
+        unit_bases<U, VG>(w0, blockDim.x, nunits, ga, base, live);
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -117,14 +124,14 @@ __global__ void __launch_bounds__(256) k_dense(C *__restrict__ psi, GroupArgs ga
 
 template <typename C, int M, int VG>
 __global__ void __launch_bounds__(256) k_diag(C *__restrict__ psi, GroupArgs ga, DiagArgs<C, M> da) {
-    constexpr int U = Unroll<M>::U;
+    constexpr int U = Unroll<C, M>::U;
     const uint64_t nunits = ga.ngroups / VG;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t w0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w0 < nunits; w0 += U * stride) {
+    const uint64_t span = (uint64_t)U * blockDim.x;
+    for (uint64_t w0 = (uint64_t)blockIdx.x * span + threadIdx.x; w0 < nunits; w0 += (uint64_t)gridDim.x * span) {
         uint64_t base[U];
         bool live[U];
         C v[U][M][VG];
-        unit_bases<U, VG>(w0, stride, nunits, ga, base, live);
+        unit_bases<U, VG>(w0, blockDim.x, nunits, ga, base, live);
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -144,14 +151,14 @@ __global__ void __launch_bounds__(256) k_diag(C *__restrict__ psi, GroupArgs ga,
 
 template <typename C, int M, int VG>
 __global__ void __launch_bounds__(256) k_perm(C *__restrict__ psi, GroupArgs ga, PermArgs<C, M> pa) {
-    constexpr int U = Unroll<M>::U;
+    constexpr int U = Unroll<C, M>::U;
     const uint64_t nunits = ga.ngroups / VG;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t w0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w0 < nunits; w0 += U * stride) {
+    const uint64_t span = (uint64_t)U * blockDim.x;
+    for (uint64_t w0 = (uint64_t)blockIdx.x * span + threadIdx.x; w0 < nunits; w0 += (uint64_t)gridDim.x * span) {
         uint64_t base[U];
         bool live[U];
         C v[U][M][VG];
-        unit_bases<U, VG>(w0, stride, nunits, ga, base, live);
+        unit_bases<U, VG>(w0, blockDim.x, nunits, ga, base, live);
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -197,21 +204,22 @@ template <typename C, int VEC>
 __global__ void __launch_bounds__(256) k_low1(C *__restrict__ psi, Low1Args<C> a) {
     constexpr int LV = (VEC == 1) ? 0 : (VEC == 2) ? 1 : 2;
     constexpr int U = 4;   // vectors per lane per iteration, all loaded before use
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    // nvec is a multiple of 64 and stride of 256, so a wave's lanes are all
-    // live or all idle for every u: the shuffles below see a full wave
-    for (uint64_t w0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w0 < a.nvec; w0 += U * stride) {
+    const uint64_t span = (uint64_t)U * blockDim.x;
+    // nvec is a multiple of 64 and a wave's 64 lanes hold 64 consecutive
+    // aligned vectors, so they are all live or all idle for every u: the
+    // shuffles below see a full wave
+    for (uint64_t w0 = (uint64_t)blockIdx.x * span + threadIdx.x; w0 < a.nvec; w0 += (uint64_t)gridDim.x * span) {
         C v[U][VEC];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint64_t w = w0 + u * stride;
+            const uint64_t w = w0 + (uint64_t)u * blockDim.x;
             if (w < a.nvec)
 #pragma unroll
                 for (int j = 0; j < VEC; ++j) v[u][j] = psi[w * VEC + j];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint64_t w = w0 + u * stride;
+            const uint64_t w = w0 + (uint64_t)u * blockDim.x;
             if (w >= a.nvec) continue;
             const uint64_t i0 = w * VEC;
             C o[VEC];
@@ -250,9 +258,11 @@ __global__ void __launch_bounds__(256) k_low1(C *__restrict__ psi, Low1Args<C> a
 
 // ------------------------------------------------------------------ launch
 
-static int grid_for(uint64_t items, int threads) {
-    uint64_t blocks = (items + threads - 1) / threads;
-    const uint64_t cap = (uint64_t)device_sm_count() * 64;   // grid-stride beyond this
+// Workgroups for `items` units at `per_block` units each: one pass over the
+// state (the loops in the kernels only run again beyond the grid limit).
+static int grid_for(uint64_t items, uint64_t per_block) {
+    uint64_t blocks = (items + per_block - 1) / per_block;
+    const uint64_t cap = 0x7fffffffull;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
     return (int)blocks;
@@ -286,8 +296,9 @@ static void launch_dense_m(C *psi, const GateAnalysis &a, const GroupArgs &ga, c
     if (M <= 8)
         for (int j = 0; j < M * M; ++j) da.mat[j] = to_c<C>(&a.mat[2 * j]);
     da.dmat = dmat;
-    if (vg2(ga)) hipLaunchKernelGGL((k_dense<C, M, 2>), dim3(grid_for(ga.ngroups / 2, 256)), dim3(256), 0, s, psi, ga, da);
-    else hipLaunchKernelGGL((k_dense<C, M, 1>), dim3(grid_for(ga.ngroups, 256)), dim3(256), 0, s, psi, ga, da);
+    constexpr int PB = 256 * Unroll<C, M>::U;
+    if (vg2(ga)) hipLaunchKernelGGL((k_dense<C, M, 2>), dim3(grid_for(ga.ngroups / 2, PB)), dim3(256), 0, s, psi, ga, da);
+    else hipLaunchKernelGGL((k_dense<C, M, 1>), dim3(grid_for(ga.ngroups, PB)), dim3(256), 0, s, psi, ga, da);
 }
 
 template <typename C, int M>
@@ -298,8 +309,9 @@ static void launch_diag_m(C *psi, const GateAnalysis &a, const GroupArgs &ga, hi
         da.offs[j] = a.offs[j];
         da.fac[j] = to_c<C>(&a.mat[2 * j]);
     }
-    if (vg2(ga)) hipLaunchKernelGGL((k_diag<C, M, 2>), dim3(grid_for(ga.ngroups / 2, 256)), dim3(256), 0, s, psi, ga, da);
-    else hipLaunchKernelGGL((k_diag<C, M, 1>), dim3(grid_for(ga.ngroups, 256)), dim3(256), 0, s, psi, ga, da);
+    constexpr int PB = 256 * Unroll<C, M>::U;
+    if (vg2(ga)) hipLaunchKernelGGL((k_diag<C, M, 2>), dim3(grid_for(ga.ngroups / 2, PB)), dim3(256), 0, s, psi, ga, da);
+    else hipLaunchKernelGGL((k_diag<C, M, 1>), dim3(grid_for(ga.ngroups, PB)), dim3(256), 0, s, psi, ga, da);
 }
 
 template <typename C, int M>
@@ -312,13 +324,14 @@ static void launch_perm_m(C *psi, const GateAnalysis &a, const GroupArgs &ga, hi
         pa.fac[j] = to_c<C>(&a.mat[2 * j]);
         if (a.perm_one[j]) pa.one |= 1ull << j;
     }
-    if (vg2(ga)) hipLaunchKernelGGL((k_perm<C, M, 2>), dim3(grid_for(ga.ngroups / 2, 256)), dim3(256), 0, s, psi, ga, pa);
-    else hipLaunchKernelGGL((k_perm<C, M, 1>), dim3(grid_for(ga.ngroups, 256)), dim3(256), 0, s, psi, ga, pa);
+    constexpr int PB = 256 * Unroll<C, M>::U;
+    if (vg2(ga)) hipLaunchKernelGGL((k_perm<C, M, 2>), dim3(grid_for(ga.ngroups / 2, PB)), dim3(256), 0, s, psi, ga, pa);
+    else hipLaunchKernelGGL((k_perm<C, M, 1>), dim3(grid_for(ga.ngroups, PB)), dim3(256), 0, s, psi, ga, pa);
 }
 
 // Low-qubit path for a one-target dense gate whose target is below the
-// lane-exchange span: the lane vector is 16 bytes (2 complex64 or 1 complex128)
-// and partners up to 64 vectors away are reached by shuffles.
+// lane-exchange span: the lane vector is 16 bytes (2 complex64) and partners
+// up to 64 vectors away are reached by shuffles.
 template <typename C, int VEC>
 static bool try_low1(C *psi, const GateAnalysis &a, hipStream_t s) {
     constexpr int LV = (VEC == 1) ? 0 : (VEC == 2) ? 1 : 2;
@@ -334,7 +347,7 @@ static bool try_low1(C *psi, const GateAnalysis &a, hipStream_t s) {
     la.cmask = a.cmask;
     la.nvec = (1ull << a.n) / VEC;
     la.t = t;
-    hipLaunchKernelGGL((k_low1<C, VEC>), dim3(grid_for(la.nvec, 256)), dim3(256), 0, s, psi, la);
+    hipLaunchKernelGGL((k_low1<C, VEC>), dim3(grid_for(la.nvec, 256 * 4)), dim3(256), 0, s, psi, la);
     return true;
 }
 
@@ -345,7 +358,9 @@ static int launch_gate_t(void *state, const GateAnalysis &a, hipStream_t s) {
     const int M = (int)a.members.size();
     if (M == 0) return QSV_OK;   // identity
     const GroupArgs ga = make_group_args(a);
-    if (a.cls == GC_DENSE && try_low1<C, sizeof(R) == 4 ? 2 : 1>(psi, a, s)) {
+    // complex64 only: a complex128 amplitude is already a full 16-byte lane
+    // access, and the group kernel streams those faster than the shuffles
+    if (sizeof(R) == 4 && a.cls == GC_DENSE && try_low1<C, 2>(psi, a, s)) {
         QSV_HIP_CHECK(hipGetLastError());
         return QSV_OK;
     }
