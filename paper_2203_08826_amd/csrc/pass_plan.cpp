@@ -560,15 +560,15 @@ int build_passes_once(qsv_plan *p, int local_bits, bool allow_fold) {
         S = 0;
         for (int q = 0; q < lanes; ++q) S |= 1ull << q;
     };
-    // local set of exactly L bits that contains S and is closed under sigma, if any
-    auto close_under_sigma = [&](uint64_t s, uint64_t &out) {
+    // local set of exactly `size` bits that contains S and is closed under sigma, if any
+    auto close_under_sigma = [&](uint64_t s, uint64_t &out, int size) {
         for (int b = 0; b < n; ++b)
             if ((s >> b) & 1) s |= 1ull << sigma[b];
-        for (int b = 0; b < n && __builtin_popcountll(s) < L; ++b)   // fixed points first
+        for (int b = 0; b < n && __builtin_popcountll(s) < size; ++b)   // fixed points first
             if (sigma[b] == b) s |= 1ull << b;
-        for (int b = 0; b < n && __builtin_popcountll(s) + 1 < L; ++b)
+        for (int b = 0; b < n && __builtin_popcountll(s) + 1 < size; ++b)
             if (!((s >> b) & 1)) s |= (1ull << b) | (1ull << sigma[b]);
-        if (__builtin_popcountll(s) != L) return false;
+        if (__builtin_popcountll(s) != size) return false;
         out = s;
         return true;
     };
@@ -576,7 +576,7 @@ int build_passes_once(qsv_plan *p, int local_bits, bool allow_fold) {
         if (run.empty()) return QSV_OK;
         const std::vector<int> *fold = nullptr;
         uint64_t Sc = 0;
-        if (!folded && allow_fold && moved && involution && close_under_sigma(S, Sc)) {
+        if (!folded && allow_fold && moved && involution && close_under_sigma(S, Sc, L)) {
             S = Sc;
             fold = &sigma;
             folded = true;
@@ -643,9 +643,39 @@ int build_passes_once(qsv_plan *p, int local_bits, bool allow_fold) {
     const double s_amp = p->dtype == QSV_C64 ? 8.0 : 16.0;
     if (involution) {
         PlanOp op;
-        op.kind = PlanOp::PERM;
-        op.sigma = sigma;
         op.bytes = 2.0 * std::ldexp(1.0, n) * s_amp;
+        // local set: the lowest bits, each with its image, so that both the
+        // loads and the stores run over the longest contiguous stretches; a
+        // chunk one bit smaller when no closed set of L bits exists
+        auto lowest_closed = [&](int size, uint64_t &out) {
+            uint64_t s = 0;
+            for (int b = 0; b < n; ++b) {
+                if ((s >> b) & 1) continue;
+                const int need = sigma[b] == b ? 1 : 2;
+                if (__builtin_popcountll(s) + need > size) continue;
+                s |= (1ull << b) | (1ull << sigma[b]);
+            }
+            out = s;
+            return __builtin_popcountll(s) == size && (s & ((1ull << lanes) - 1ull)) == (1ull << lanes) - 1ull;
+        };
+        uint64_t Sp = 0;
+        int rbp = RB;
+        bool closed = lowest_closed(L, Sp);
+        if (!closed && RB > 1) closed = lowest_closed(L - 1, Sp), rbp = RB - 1;
+        if (p->opts.jit && closed) {
+            // compiled plans: a pass without gates whose store applies sigma
+            std::vector<int> local;
+            for (int q = 0; q < n; ++q)
+                if ((Sp >> q) & 1) local.push_back(q);
+            auto prog = std::make_shared<PassProgram>();
+            int st2 = compile_pass(n, {}, local, rbp, *prog, &sigma);
+            if (st2) return st2;
+            op.kind = PlanOp::PASS;
+            op.pass = prog;
+        } else {
+            op.kind = PlanOp::PERM;
+            op.sigma = sigma;
+        }
         p->ops.push_back(std::move(op));
         p->stats.n_passes++;
         return QSV_OK;

@@ -75,17 +75,19 @@ __global__ void __launch_bounds__(BP_THREADS) k_bitperm(BpC<R> *__restrict__ psi
         lm_hi[x] = mhi;
     }
     __syncthreads();
-    // Persistent workgroups walk the work items; item w is the chunk whose
-    // non-local bits are w's bits in the order a.order (the lowest non-local
-    // bits and their images under sigma vary fastest, so the workgroups
-    // running at the same time read contiguous runs on both sides of their
-    // pairs).  The workgroup of the smaller base of a pair moves both.
+    // One work item per workgroup (a one-shot grid: the hardware starts the
+    // next workgroups while earlier ones store, which keeps loads and stores
+    // overlapped).  Item w is the chunk whose non-local bits are w's bits in
+    // the order a.order (the lowest non-local bits and their images under
+    // sigma vary fastest, so neighbouring workgroups read contiguous runs on
+    // both sides of their pairs).  The workgroup of the smaller base of a pair
+    // moves both; the other one exits at once.
     const int nn = a.n - L;
     for (uint64_t w = blockIdx.x; w < a.nchunks; w += gridDim.x) {
         uint64_t base = 0;
         for (int j = 0; j < nn; ++j) base |= ((w >> j) & 1ull) << a.order[j];
         const uint64_t pbase = bp_permute_global(base, a);   // non-local bits only (local set is closed)
-        if (pbase < base) continue;   // uniform: the partner's iteration moves this pair
+        if (pbase < base) continue;   // uniform: the partner's item moves this pair
         const bool pair = pbase != base;
         // Both chunks are loaded before anything is stored; each thread writes
         // its loaded values to LDS before the barrier that precedes the first
@@ -197,21 +199,7 @@ int launch_bitperm(void *state, int n, int dtype, const std::vector<int> &sigma,
             if (a.lpos[k] == dst) a.lperm[i] = k;
     }
     a.nchunks = 1ull << (n - L);
-    // persistent grid: as many workgroups as can be resident
-    static int resident[2][64] = {{0}};
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    if (dev < 0 || dev >= 64) dev = 0;
-    const int di = dtype == QSV_C64 ? 0 : 1;
-    if (resident[di][dev] == 0) {
-        int per_cu = 0;
-        hipError_t e = dtype == QSV_C64
-                           ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bitperm<float>, BP_THREADS, 0)
-                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bitperm<double>, BP_THREADS, 0);
-        if (e != hipSuccess || per_cu < 1) per_cu = 1;
-        resident[di][dev] = per_cu;
-    }
-    const unsigned grid = (unsigned)std::min<uint64_t>(a.nchunks, (uint64_t)resident[di][dev] * device_sm_count());
+    const unsigned grid = (unsigned)std::min<uint64_t>(a.nchunks, 0x7fffffffull);
     if (dtype == QSV_C64)
         hipLaunchKernelGGL(k_bitperm<float>, dim3(grid), dim3(BP_THREADS), 0, s, (BpC<float> *)state, a);
     else
