@@ -124,6 +124,9 @@ def test_final_permutation_folds_only_when_it_saves_a_sweep():
     kinds = lambda p: [qsv.qsv_plan_op_info(p, i)["kind"] for i in range(p.stats()["n_launches"])]
     assert kinds(qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_PASSES, local_bits=12)) == [2, 3]
     assert kinds(qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_PASSES, local_bits=12, jit=1)) == [2]
-    # the 30-qubit QFT would need one more pass to fold its reversal: kept as a permutation sweep
-    q = qsv.qsv_plan_create(30, qsv.QSV_C64, W.qft(30), mode=qsv.PLAN_PASSES, local_bits=12, jit=1)
-    assert kinds(q)[-1] == 3 and len(kinds(q)) == 5
+    # the 30-qubit QFT would need one more pass to fold its reversal: it stays a separate sweep,
+    # the permutation kernel when interpreted, a gate-free compiled pass when compiled
+    qi = qsv.qsv_plan_create(30, qsv.QSV_C64, W.qft(30), mode=qsv.PLAN_PASSES, local_bits=12)
+    assert kinds(qi) == [2, 2, 2, 2, 3]
+    qc = qsv.qsv_plan_create(30, qsv.QSV_C64, W.qft(30), mode=qsv.PLAN_PASSES, local_bits=12, jit=1)
+    assert kinds(qc) == [2, 2, 2, 2, 2] and qc.stats()["n_jit_passes"] == 5
