@@ -158,7 +158,10 @@ enum { QSV_PLAN_PER_GATE = 0, QSV_PLAN_GREEDY = 1, QSV_PLAN_PASSES = 2, QSV_PLAN
 typedef struct qsv_plan_options {
     int mode;          /* QSV_PLAN_* */
     int kmax;          /* fusion width for QSV_PLAN_GREEDY, 1..6 (default 2) */
-    int local_bits;    /* chunk bits for QSV_PLAN_PASSES, 0 = library default */
+    int local_bits;    /* chunk bits for QSV_PLAN_PASSES, 0 = library default (the
+                        * largest): interpreted passes take 9..13 (complex64) or
+                        * 9..12 (complex128), compiled passes (512-thread
+                        * workgroups) 10..14 or 10..13 */
     int use_mfma;      /* 1: fused complex64 blocks of 4..6 qubits use MFMA */
     int jit;           /* 1: every LDS pass of the plan is compiled (hiprtc, at
                         * qsv_plan_create) into a kernel specialised for its

@@ -33,8 +33,8 @@ def candidate_configs(n, dtype, jit=(0, 1)):
     out = [("per_gate", dict(mode=PLAN_PER_GATE))]
     for k in range(2, 6):
         out.append(("greedy%d" % k, dict(mode=PLAN_GREEDY, kmax=k, use_mfma=1)))
-    ld = (5 if dtype == QSV_C64 else 4) + 8
     for j in jit:
+        ld = (5 if dtype == QSV_C64 else 4) + (9 if j else 8)   # compiled passes: 512-thread workgroups
         sfx = "_jit" if j else ""
         if n >= ld:
             out.append(("passes%d%s" % (ld, sfx), dict(mode=PLAN_PASSES, local_bits=ld, jit=j)))

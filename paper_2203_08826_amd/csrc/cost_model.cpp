@@ -158,7 +158,7 @@ int build_learned(qsv_plan *p) {
     owned.push_back(candidate(p, QSV_PLAN_PER_GATE, 1, 0, 0));
     for (int k = 2; k <= 5; ++k) owned.push_back(candidate(p, QSV_PLAN_GREEDY, k, 0, mf));
     const int rb_max = p->dtype == QSV_C64 ? 5 : 4;
-    const int Ld = rb_max + PASS_THREAD_BITS;
+    const int Ld = rb_max + (p->opts.jit ? PASS_JIT_THREAD_BITS : PASS_THREAD_BITS);
     if (p->n >= Ld) owned.push_back(candidate(p, QSV_PLAN_PASSES, 0, Ld, 0));
     if (p->n >= Ld - 1) owned.push_back(candidate(p, QSV_PLAN_PASSES, 0, Ld - 1, 0));
     std::vector<const qsv_plan *> cands;

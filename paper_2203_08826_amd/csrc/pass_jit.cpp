@@ -50,6 +50,14 @@ struct JitModule {
     }
 };
 
+// Persistent workgroups that load the next chunk while computing the current
+// one, when two register tiles fit (not for chunk pairs, which hold two tiles
+// already); otherwise one chunk per workgroup.
+bool pass_jit_prefetch(const PassProgram &p, int dtype) {
+    if (!p.pair_sigma.empty()) return false;
+    return dtype == QSV_C64 ? p.RB <= 4 : p.RB <= 3;
+}
+
 // Enumeration order of the non-local bits (mask ~local over sigma's bits)
 // for chunk-pair work: the lowest K non-local bits, then their images under
 // sigma, then the rest ascending.
@@ -155,7 +163,7 @@ std::string Gen::comb(const std::vector<std::pair<std::pair<double, double>, std
 // thread bits u of bit u of t shifted to its position.
 std::string Gen::thread_offset(const PassPartition &part, const int *pos, bool global) const {
     std::string e;
-    for (int u = 0; u < PASS_THREAD_BITS; ++u) {
+    for (int u = 0; u < P.TB; ++u) {
         const int p = pos ? pos[part.thr_l[u]] : part.thr_l[u];
         if (!e.empty()) e += " | ";
         if (global) e += fmt("((unsigned long long)((t >> %d) & 1u) << %d)", u, p);
@@ -299,7 +307,7 @@ void Gen::phase(const PassOpDev &op, int sk) {
 std::string Gen::source() {
     const int L = P.L, RB = P.RB;
     const bool pair = !P.pair_sigma.empty();
-    const bool PF = !pair && (f32 ? RB <= 4 : RB <= 3);
+    const bool PF = pass_jit_prefetch(P, f32 ? QSV_C64 : QSV_C128);
     bool any_exchange = false;
     for (auto &op : P.ops)
         if (op.kind == POP_EXCHANGE) any_exchange = true;
@@ -338,9 +346,9 @@ std::string Gen::source() {
     ln("    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, \"workgroup\", \"local\"); }");
     ln("__device__ __forceinline__ unsigned swz(unsigned l) { return l ^ (((l >> 4) ^ (l >> 8) ^ (l >> 12)) & 15u); }");
     ln("");
-    ln(fmt("extern \"C\" __global__ void __launch_bounds__(256) %s(C *__restrict__ psi, const unsigned char "
+    ln(fmt("extern \"C\" __global__ void __launch_bounds__(%d) %s(C *__restrict__ psi, const unsigned char "
            "*__restrict__ prog, unsigned long long nchunks) {",
-           JIT_KERNEL_NAME));
+           1 << P.TB, JIT_KERNEL_NAME));
     if (any_exchange) ln(fmt("    __shared__ C lds[%d];", 1 << L));
     ln(fmt("    const R *pool = (const R *)(prog + %d);", pool_offset));
     ln("    (void)pool;");
@@ -625,7 +633,8 @@ int launch_pass_jit(void *state, int n, int dtype, const PassProgram &prog, hipS
             if ((e = hipModuleGetFunction(&ld.fn, ld.mod, JIT_KERNEL_NAME)) != hipSuccess)
                 return hip_fail(e, "finding the compiled pass kernel");
             int b = 0;
-            if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&b, ld.fn, 256, 0) != hipSuccess || b < 1) b = 1;
+            if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&b, ld.fn, 1 << prog.TB, 0) != hipSuccess || b < 1)
+                b = 1;
             ld.grid_per_cu = b;
         }
         fn = ld.fn;
@@ -635,12 +644,12 @@ int launch_pass_jit(void *state, int n, int dtype, const PassProgram &prog, hipS
     int st = upload_pass_program(prog, dtype, s, &slot);
     if (st) return st;
     uint64_t nchunks = 1ull << (n - prog.L);
-    const bool pf = dtype == QSV_C64 ? prog.RB <= 4 : prog.RB <= 3;
+    const bool pf = pass_jit_prefetch(prog, dtype);
     uint64_t g = pf ? (uint64_t)per_cu * device_sm_count() : std::min<uint64_t>(nchunks, 1ull << 20);
     if (g > nchunks) g = nchunks;
     void *dprog = slot.dev;
     void *args[] = {&state, &dprog, &nchunks};
-    e = hipModuleLaunchKernel(fn, (unsigned)g, 1, 1, 256, 1, 1, 0, s, args, nullptr);
+    e = hipModuleLaunchKernel(fn, (unsigned)g, 1, 1, 1u << prog.TB, 1, 1, 0, s, args, nullptr);
     staging_release(slot, s);
     if (e != hipSuccess) return hip_fail(e, "compiled pass kernel launch");
     return QSV_OK;

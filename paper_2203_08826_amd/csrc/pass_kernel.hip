@@ -565,7 +565,8 @@ int upload_pass_program(const PassProgram &prog, int dtype, hipStream_t s, Stagi
 }
 
 int launch_pass_program(void *state, int n, int dtype, const PassProgram &prog, hipStream_t s) {
-    if (!prog.pair_sigma.empty()) return fail(QSV_ERR_UNSUPPORTED, "internal: chunk-pair pass needs its compiled kernel");
+    if (!prog.pair_sigma.empty() || prog.TB != PASS_THREAD_BITS)
+        return fail(QSV_ERR_UNSUPPORTED, "internal: this pass program needs its compiled kernel");
     StagingSlot slot;
     int st = upload_pass_program(prog, dtype, s, &slot);
     if (st) return st;

@@ -162,6 +162,7 @@ int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> 
     const int L = (int)local.size();
     prog.L = L;
     prog.RB = RB;
+    prog.TB = L - RB;
     prog.local_sorted = local;
     std::sort(prog.local_sorted.begin(), prog.local_sorted.end());
     int lpos[QSV_MAX_QUBITS];
@@ -338,12 +339,12 @@ int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> 
         for (int g = 0; g <= PASS_MAX_RB; ++g) d.tab[g] = -1;
         for (int g = 0; g <= RB; ++g) {
             if (thr[g].empty()) continue;
-            if (prog.pool.size() + 512 > 16384) {
+            if (prog.pool.size() + (2u << prog.TB) > 16384) {
                 for (auto &td : thr[g]) chunk[{g, td.mt}].push_back(td);   // evaluated as slots instead
                 continue;
             }
             d.tab[g] = (int)prog.pool.size();
-            for (uint32_t tt = 0; tt < 256; ++tt) {
+            for (uint32_t tt = 0; tt < (1u << prog.TB); ++tt) {
                 uint64_t ph = 0;
                 for (auto &td : thr[g])
                     if ((tt & td.mt) == td.mt) ph += td.theta;
@@ -479,7 +480,7 @@ int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> 
         PassPartition pp;
         std::memset(&pp, 0, sizeof(pp));
         for (int i = 0; i < RB; ++i) pp.reg_l[i] = p.reg[i];
-        for (int u = 0; u < PASS_THREAD_BITS; ++u) pp.thr_l[u] = p.thr[u];
+        for (int u = 0; u < prog.TB; ++u) pp.thr_l[u] = p.thr[u];
         prog.parts.push_back(pp);
     }
     prog.n_gates = (int)gates.size();
@@ -489,11 +490,13 @@ int compile_pass(int n, const std::vector<PGate> &gates, const std::vector<int> 
 
 }  // namespace
 
-int pass_register_bits(int n, int dtype, int local_bits) {
+// Register bits of a chunk of `local_bits` local qubits (0: the largest) in
+// a workgroup of 2^tb threads; -1 when no valid chunk exists.
+int pass_register_bits(int n, int dtype, int local_bits, int tb) {
     const int rb_max = dtype == QSV_C64 ? 5 : 4;
-    int L = local_bits > 0 ? local_bits : rb_max + PASS_THREAD_BITS;
+    int L = local_bits > 0 ? local_bits : rb_max + tb;
     if (L > n) L = n;
-    const int RB = L - PASS_THREAD_BITS;
+    const int RB = L - tb;
     if (RB < 1 || RB > rb_max) return -1;
     return RB;
 }
@@ -502,7 +505,8 @@ namespace {
 
 int build_passes_once(qsv_plan *p, int local_bits, bool allow_fold) {
     const int n = p->n;
-    const int RB = pass_register_bits(n, p->dtype, local_bits);
+    const int TB = p->opts.jit ? PASS_JIT_THREAD_BITS : PASS_THREAD_BITS;
+    const int RB = pass_register_bits(n, p->dtype, local_bits, TB);
     if (local_bits > 0 && RB < 0) return fail(QSV_ERR_ARG, "local_bits outside the supported range");
     if (RB < 0) {
         // too few qubits for a chunk: per-gate launches
@@ -512,7 +516,7 @@ int build_passes_once(qsv_plan *p, int local_bits, bool allow_fold) {
         }
         return QSV_OK;
     }
-    const int L = RB + PASS_THREAD_BITS;
+    const int L = RB + TB;
     const int lanes = std::min(LANE_BITS, L - RB);
     // SWAP gates become relabellings: logical qubit q lives at physical bit
     // phys[q]; every other gate is rewritten onto physical bits.
@@ -733,7 +737,7 @@ int build_passes(qsv_plan *p, int local_bits) {
 int build_single_pass(int n, int dtype, const std::vector<qsv_gate> &gates, const std::vector<int> &local,
                       PassProgram &out) {
     const int L = (int)local.size();
-    const int RB = pass_register_bits(n, dtype, L);
+    const int RB = pass_register_bits(n, dtype, L, PASS_THREAD_BITS);
     if (RB < 0 || L != RB + PASS_THREAD_BITS) return fail(QSV_ERR_ARG, "nlocal must be in [9, 13] (complex64) or [9, 12] (complex128) and <= n");
     uint64_t S = 0;
     for (int q : local) {

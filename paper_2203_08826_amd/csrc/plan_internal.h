@@ -13,15 +13,19 @@ namespace qsv {
 //
 // A pass processes the state chunk by chunk.  A chunk is the set of 2^L
 // amplitudes that share every non-local bit; the L local bits of an index
-// are numbered l = 0..L-1 ("local positions").  A workgroup of 256 threads
-// holds one chunk: thread t keeps 2^RB amplitudes in registers (L = RB + 8).
+// are numbered l = 0..L-1 ("local positions").  A workgroup of 2^TB threads
+// holds one chunk: thread t keeps 2^RB amplitudes in registers (L = RB + TB;
+// TB = 8 for the interpreted kernel, 9 for compiled passes, whose straight-
+// line code leaves room for 512-thread workgroups and 128 KiB chunks).
 // A "partition" says which local positions are register bits (j index) and
-// which are thread bits (t index: bits 0..5 lane, 6..7 wave).  Ops act on
+// which are thread bits (t index: bits 0..5 lane, the rest wave).  Ops act on
 // register bits; an EXCHANGE op moves to another partition through LDS.
 
-constexpr int PASS_THREAD_BITS = 8;
+constexpr int PASS_THREAD_BITS = 8;        // interpreted kernel
+constexpr int PASS_JIT_THREAD_BITS = 9;    // compiled passes
+constexpr int PASS_MAX_THREAD_BITS = 9;
 constexpr int PASS_MAX_RB = 5;
-constexpr int PASS_MAX_L = PASS_MAX_RB + PASS_THREAD_BITS;
+constexpr int PASS_MAX_L = PASS_MAX_RB + PASS_MAX_THREAD_BITS;
 constexpr int PASS_MAX_SLOTS = 64;       // per op: one per lane of a wave
 constexpr int PASS_SLOT_TERMS = 32;      // longer slots are split
 
@@ -29,7 +33,7 @@ enum PassOpKind : int32_t { POP_EXCHANGE = 1, POP_G1 = 2, POP_G1R = 3, POP_G2 = 
 
 struct PassPartition {
     int32_t reg_l[PASS_MAX_RB];          // local position of register bit i
-    int32_t thr_l[PASS_THREAD_BITS];     // local position of thread bit u
+    int32_t thr_l[PASS_MAX_THREAD_BITS]; // local position of thread bit u (u < TB)
 };
 
 // Phase evaluation (PHASE ops, and the phase a G1/G1R op applies to its
@@ -98,6 +102,7 @@ struct JitModule;   // a pass program compiled into a kernel of its own (pass_ji
 struct PassProgram {
     int L = 0;
     int RB = 0;
+    int TB = PASS_THREAD_BITS;            // thread bits (workgroup of 2^TB threads)
     std::vector<int> local_sorted;        // global bits of local positions at load (ascending)
     std::vector<int> out_pos;             // global bit of local position l at store
     std::vector<PassPartition> parts;
@@ -118,6 +123,7 @@ int launch_pass_program(void *state, int n, int dtype, const PassProgram &prog, 
 int launch_pass_jit(void *state, int n, int dtype, const PassProgram &prog, hipStream_t s);
 std::string pass_jit_source(const PassProgram &prog, int dtype);
 std::vector<int> pair_chunk_order(const std::vector<int> &sigma, uint64_t local);
+bool pass_jit_prefetch(const PassProgram &p, int dtype);
 int launch_bitperm(void *state, int n, int dtype, const std::vector<int> &sigma, hipStream_t s);
 
 // ---------------------------------------------------------------- plans
