@@ -51,10 +51,13 @@ struct JitModule {
 };
 
 // Persistent workgroups that load the next chunk while computing the current
-// one, when two register tiles fit (not for chunk pairs, which hold two tiles
-// already); otherwise one chunk per workgroup.
+// one, when two register tiles fit without spills (not for chunk pairs, which
+// hold two tiles already); otherwise one chunk per workgroup.  A 512-thread
+// workgroup of 14 local qubits fills a CU's LDS alone, so without this the
+// memory pipe of its CU would idle while it computes.
 bool pass_jit_prefetch(const PassProgram &p, int dtype) {
     if (!p.pair_sigma.empty()) return false;
+    if (p.TB == PASS_JIT_THREAD_BITS) return dtype == QSV_C64 ? p.RB <= 5 : p.RB <= 3;
     return dtype == QSV_C64 ? p.RB <= 4 : p.RB <= 3;
 }
 

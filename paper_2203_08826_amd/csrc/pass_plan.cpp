@@ -662,10 +662,24 @@ int build_passes_once(qsv_plan *p, int local_bits, bool allow_fold) {
             out = s;
             return __builtin_popcountll(s) == size && (s & ((1ull << lanes) - 1ull)) == (1ull << lanes) - 1ull;
         };
+        // (at most 12 local bits when sigma moves a lane bit, which takes an
+        // LDS exchange: the pass has no gates to amortise, and a 32 KiB chunk
+        // lets several workgroups share a CU, so one's loads overlap
+        // another's exchange and stores; without an exchange the largest
+        // chunk streams best)
+        bool moves_lanes = false;
+        for (int b = 0; b < lanes; ++b)
+            if (sigma[b] != b) moves_lanes = true;
         uint64_t Sp = 0;
-        int rbp = RB;
-        bool closed = lowest_closed(L, Sp);
-        if (!closed && RB > 1) closed = lowest_closed(L - 1, Sp), rbp = RB - 1;
+        int rbp = -1;
+        const int l12 = std::min(L, 12);
+        const int order[4] = {moves_lanes ? l12 : L, moves_lanes ? l12 - 1 : L - 1, moves_lanes ? L : l12,
+                              moves_lanes ? L - 1 : l12 - 1};
+        for (int size : order) {
+            if (size - TB < 1 || rbp >= 0) continue;
+            if (lowest_closed(size, Sp)) rbp = size - TB;
+        }
+        const bool closed = rbp >= 1;
         if (p->opts.jit && closed) {
             // compiled plans: a pass without gates whose store applies sigma
             std::vector<int> local;
