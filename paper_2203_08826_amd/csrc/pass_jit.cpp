@@ -123,6 +123,7 @@ class Gen {
     const int pool_offset;   // byte offset of the real pool in the serialised program
     std::string s;
     int uid = 0;
+    double scale = 1.0;   // real factor owed by every amplitude of the tile (see gate())
 
     void ln(const std::string &x) { s += x, s += '\n'; }
     double R(double v) const { return f32 ? (double)(float)v : v; }   // value as the kernel's real type holds it
@@ -176,9 +177,32 @@ std::string Gen::thread_offset(const PassPartition &part, const int *pos, bool g
 }
 
 // One- or two-qubit gate on register bits (bits[0] = the matrix index MSB).
-void Gen::gate(const PassOpDev &op, const std::vector<int> &bits, const std::vector<double> &M, bool real) {
+void Gen::gate(const PassOpDev &op, const std::vector<int> &bits, const std::vector<double> &M0, bool real) {
     const int k = (int)bits.size(), d = 1 << k;
     const bool tok = op.ct != 0 || op.cn != 0;
+    // An uncontrolled gate whose nonzero entries all have one magnitude m
+    // (H, the square roots of X and Y, ...) acts on every amplitude of the
+    // tile, so m can be factored out: the gate's skeleton M / m (entries of
+    // modulus 1, often +-1 and +-i: additions only) runs here and m joins the
+    // real factor that the pass applies once before its store (every op of a
+    // pass is linear, so the factor commutes with the rest).
+    std::vector<double> M = M0;
+    if (!tok && op.cj == 0) {
+        double mag = -1.0;
+        bool same = true;
+        const int ne = d * d;
+        for (int e = 0; e < ne && same; ++e) {
+            const double re = real ? M[e] : M[2 * e], im = real ? 0.0 : M[2 * e + 1];
+            const double a = std::hypot(re, im);
+            if (a == 0.0) continue;
+            if (mag < 0) mag = a;
+            else if (std::fabs(a - mag) > 1e-15 * mag) same = false;
+        }
+        if (same && mag > 0 && mag != 1.0) {
+            for (double &x : M) x /= mag;
+            scale *= mag;
+        }
+    }
     if (tok) ln(fmt("        { const bool tk = ((t & %uu) == %uu) && ((base & %s) == %s);", op.ct, op.ct,
                     u64(op.cn).c_str(), u64(op.cn).c_str()));
     else ln("        {");
@@ -468,6 +492,11 @@ std::string Gen::source() {
         }
         default: break;
         }
+    }
+    if (scale != 1.0) {
+        std::string e = "        {";
+        for (int j = 0; j < NR; ++j) e += fmt(" v[%d].x *= %s; v[%d].y *= %s;", j, lit(scale).c_str(), j, lit(scale).c_str());
+        ln(e + " }");
     }
     ln("    };");
     ln(fmt("    C v[%d];", NR));
