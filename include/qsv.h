@@ -213,6 +213,15 @@ int qsv_plan_op_program(const qsv_plan *plan, int index, void *buf, size_t cap, 
  * compiles to when the plan is built with opts->jit, NUL-terminated, into
  * buf (cap bytes); *size receives the length including the NUL. */
 int qsv_plan_op_source(const qsv_plan *plan, int index, char *buf, size_t cap, size_t *size);
+/* Host-only: the circuit indices (positions in the gate array given to
+ * qsv_plan_create) of the gates op `index` applies, in the order it applies
+ * them, into ids (cap entries); *count receives their number (ids may be
+ * NULL to query it).  A pass planner may move a gate ahead of earlier gates
+ * it commutes with, so the concatenation over all ops is a reordering of the
+ * circuit.  Uncontrolled SWAP gates that the pass planner absorbs as qubit
+ * relabellings, and the permutation that undoes them at the end, are listed
+ * by no op. */
+int qsv_plan_op_gates(const qsv_plan *plan, int index, int *ids, size_t cap, size_t *count);
 void qsv_plan_destroy(qsv_plan *plan);
 
 /* Dense fused block on FP32 matrix cores (complex64 only): Y = G X with X

@@ -288,6 +288,15 @@ def qsv_plan_op_source(plan, index):
     return buf.value.decode()
 
 
+def qsv_plan_op_gates(plan, index):
+    """Circuit indices of the gates op `index` applies, in application order."""
+    count = ctypes.c_size_t(0)
+    check("qsv_plan_op_gates", load().qsv_plan_op_gates(plan._h, int(index), None, 0, ctypes.byref(count)))
+    ids = (ctypes.c_int * max(count.value, 1))()
+    check("qsv_plan_op_gates", load().qsv_plan_op_gates(plan._h, int(index), ids, count.value, ctypes.byref(count)))
+    return [int(ids[i]) for i in range(count.value)]
+
+
 def qsv_plan_destroy(plan):
     if plan._h:
         load().qsv_plan_destroy(plan._h)

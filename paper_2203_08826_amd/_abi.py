@@ -75,6 +75,7 @@ SIGNATURES = {
     "qsv_plan_op_info": ([_vp, _i, _vp, _vp, _vp], _i),
     "qsv_plan_op_program": ([_vp, _i, _vp, ctypes.c_size_t, _vp], _i),
     "qsv_plan_op_source": ([_vp, _i, _vp, ctypes.c_size_t, _vp], _i),
+    "qsv_plan_op_gates": ([_vp, _i, _vp, ctypes.c_size_t, _vp], _i),
     "qsv_apply_block": ([_vp, _i, _i, _vp, _vp, _i, _vp], _i),
     "qsv_run_pass": ([_vp, _i, _i, _vp, _i, _vp, _i, _vp], _i),
     "qsv_probabilities": ([_vp, _i, _i, _vp, _i, _vp, _vp], _i),

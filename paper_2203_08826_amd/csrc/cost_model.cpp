@@ -128,8 +128,8 @@ static std::unique_ptr<qsv_plan> candidate(const qsv_plan *p, int mode, int kmax
     std::memset(&c->stats, 0, sizeof(c->stats));
     int st = QSV_OK;
     if (mode == QSV_PLAN_PER_GATE) {
-        for (const auto &g : c->gates)
-            if ((st = plan_add_gate_op(c.get(), g))) break;
+        for (size_t i = 0; i < c->gates.size() && !st; ++i)
+            if (!(st = plan_add_gate_op(c.get(), c->gates[i]))) c->ops.back().gate_ids = {(int)i};
     } else if (mode == QSV_PLAN_GREEDY) {
         st = build_greedy(c.get(), kmax, use_mfma != 0);
     } else {

@@ -510,9 +510,10 @@ int build_passes_once(qsv_plan *p, int local_bits, bool allow_fold) {
     if (local_bits > 0 && RB < 0) return fail(QSV_ERR_ARG, "local_bits outside the supported range");
     if (RB < 0) {
         // too few qubits for a chunk: per-gate launches
-        for (const auto &g : p->gates) {
-            int st = plan_add_gate_op(p, g);
+        for (size_t i = 0; i < p->gates.size(); ++i) {
+            int st = plan_add_gate_op(p, p->gates[i]);
             if (st) return st;
+            p->ops.back().gate_ids = {(int)i};
         }
         return QSV_OK;
     }
@@ -523,11 +524,14 @@ int build_passes_once(qsv_plan *p, int local_bits, bool allow_fold) {
     std::vector<int> phys(n);
     for (int q = 0; q < n; ++q) phys[q] = q;
     std::vector<qsv_gate> gates;
-    for (const auto &g0 : p->gates) {
+    std::vector<int> circuit_index;   // gates[k] is gate circuit_index[k] of the circuit
+    for (size_t i0 = 0; i0 < p->gates.size(); ++i0) {
+        const qsv_gate &g0 = p->gates[i0];
         if (g0.kind == QSV_GATE_SWAP && g0.c == 0) {
             std::swap(phys[g0.targets[0]], phys[g0.targets[1]]);
             continue;
         }
+        circuit_index.push_back((int)i0);
         qsv_gate g = g0;
         for (int j = 0; j < g.k; ++j) g.targets[j] = phys[g0.targets[j]];
         for (int j = 0; j < g.c; ++j) g.controls[j] = phys[g0.controls[j]];
@@ -542,36 +546,60 @@ int build_passes_once(qsv_plan *p, int local_bits, bool allow_fold) {
         if (pgs[i].kind == PGate::NONDIAG && pgs[i].targets.size() > (size_t)RB) pgs[i].kind = PGate::OTHER;
     }
     // The relabelling left at the end (data of logical qubit q sits at bit
-    // phys[q]) is undone by sigma.  With compiled passes an involution is
-    // folded into the first pass whose local set can be closed under it: that
-    // pass stores its result permuted (P_sigma V_1), and every later gate is
-    // relabelled through sigma, since P_sigma V_2 V_1 = (P_sigma V_2
-    // P_sigma^-1) P_sigma V_1.  Otherwise a bit-permutation kernel (or SWAPs)
-    // runs at the end.
+    // phys[q]) is undone by sigma, written as a product of at most two
+    // involutions (a cycle is the product of two reflections of it).  With
+    // compiled passes each involution in turn is folded into the next pass
+    // whose local set can be closed under it: that pass stores its result
+    // permuted (P_tau V_1), and every later gate is relabelled through tau,
+    // since P_tau V_2 V_1 = (P_tau V_2 P_tau^-1) P_tau V_1.  Involutions left
+    // over run as permutation sweeps at the end (or a few SWAPs).
     std::vector<int> sigma(n);
     bool moved = false;
     for (int q = 0; q < n; ++q) {
         sigma[phys[q]] = q;
         if (phys[q] != q) moved = true;
     }
-    bool involution = true;
-    for (int b = 0; b < n; ++b)
-        if (sigma[sigma[b]] != b) involution = false;
-    bool folded = false;
+    std::vector<std::vector<int>> pending;   // involutions to apply, first one first
+    int nswaps = 0;                          // SWAPs that would undo sigma instead
+    if (moved) {
+        // cycle c_0 -> c_1 -> ... -> c_{k-1}: tau_1(c_i) = c_{-i}, tau_2(c_i) = c_{1-i} (indices mod k)
+        std::vector<int> t1(n), t2(n), seen(n, 0);
+        for (int b = 0; b < n; ++b) {
+            if (seen[b]) continue;
+            std::vector<int> cyc;
+            for (int c = b; !seen[c]; c = sigma[c]) {
+                seen[c] = 1;
+                cyc.push_back(c);
+            }
+            const int k = (int)cyc.size();
+            nswaps += k - 1;
+            for (int i = 0; i < k; ++i) {
+                t1[cyc[i]] = cyc[(k - i) % k];
+                t2[cyc[i]] = cyc[(k + 1 - i) % k];
+            }
+        }
+        bool t1_id = true;
+        for (int b = 0; b < n; ++b)
+            if (t1[b] != b) t1_id = false;
+        if (!t1_id) pending.push_back(t1);
+        pending.push_back(t2);
+    }
+    size_t nfolded = 0;        // pending involutions already folded into passes
+    bool relabel_due = false;  // the last fold still has to relabel the gates not yet placed
     std::vector<PGate> run;
     uint64_t S = 0;   // local set (global bits) of the open pass
     auto reset_local = [&]() {
         S = 0;
         for (int q = 0; q < lanes; ++q) S |= 1ull << q;
     };
-    // local set of exactly `size` bits that contains S and is closed under sigma, if any
-    auto close_under_sigma = [&](uint64_t s, uint64_t &out, int size) {
+    // local set of exactly `size` bits that contains s and is closed under the involution t, if any
+    auto close_under = [&](const std::vector<int> &t, uint64_t s, uint64_t &out, int size) {
         for (int b = 0; b < n; ++b)
-            if ((s >> b) & 1) s |= 1ull << sigma[b];
+            if ((s >> b) & 1) s |= 1ull << t[b];
         for (int b = 0; b < n && __builtin_popcountll(s) < size; ++b)   // fixed points first
-            if (sigma[b] == b) s |= 1ull << b;
+            if (t[b] == b) s |= 1ull << b;
         for (int b = 0; b < n && __builtin_popcountll(s) + 1 < size; ++b)
-            if (!((s >> b) & 1)) s |= (1ull << b) | (1ull << sigma[b]);
+            if (!((s >> b) & 1)) s |= (1ull << b) | (1ull << t[b]);
         if (__builtin_popcountll(s) != size) return false;
         out = s;
         return true;
@@ -580,10 +608,11 @@ int build_passes_once(qsv_plan *p, int local_bits, bool allow_fold) {
         if (run.empty()) return QSV_OK;
         const std::vector<int> *fold = nullptr;
         uint64_t Sc = 0;
-        if (!folded && allow_fold && moved && involution && close_under_sigma(S, Sc, L)) {
+        if (allow_fold && nfolded < pending.size() && close_under(pending[nfolded], S, Sc, L)) {
             S = Sc;
-            fold = &sigma;
-            folded = true;
+            fold = &pending[nfolded];
+            ++nfolded;
+            relabel_due = true;
         }
         // fill the local set with the lowest missing bits
         for (int q = 0; q < n && __builtin_popcountll(S) < L; ++q) S |= 1ull << q;
@@ -602,6 +631,7 @@ int build_passes_once(qsv_plan *p, int local_bits, bool allow_fold) {
         for (auto &g : run) fl += g.kind == PGate::NONDIAG ? (g.targets.size() == 1 ? 8.0 : 16.0) * std::ldexp(1.0, n)
                                                             : 0.0;
         op.flops = fl;
+        for (auto &g : run) op.gate_ids.push_back(circuit_index[g.gi]);
         p->ops.push_back(std::move(op));
         p->stats.n_passes++;
         run.clear();
@@ -609,67 +639,140 @@ int build_passes_once(qsv_plan *p, int local_bits, bool allow_fold) {
         return QSV_OK;
     };
     reset_local();
-    bool relabelled = false;   // gates from here on are relabelled through sigma
-    auto sync_relabel = [&](size_t from) {
-        if (!folded || relabelled) return;
-        relabelled = true;
-        for (size_t k = from; k < pgs.size(); ++k) {
-            relabel_gate(pgs[k], sigma);
-            relabel_gate(gates[k], sigma);
+    std::vector<char> done(pgs.size(), 0);
+    auto sync_relabel = [&]() {   // gates not yet placed follow the last fold
+        if (!relabel_due) return;
+        relabel_due = false;
+        const std::vector<int> &t = pending[nfolded - 1];
+        for (size_t k = 0; k < pgs.size(); ++k)
+            if (!done[k]) {
+                relabel_gate(pgs[k], t);
+                relabel_gate(gates[k], t);
+            }
+    };
+    auto needed = [](const PGate &g) {
+        uint64_t m = 0;
+        if (g.kind == PGate::NONDIAG || g.kind == PGate::SWAP)
+            for (int q : g.targets) m |= 1ull << q;
+        return m;
+    };
+    // qubits a gate acts on non-diagonally (its targets, unless it is a
+    // phase gate) and diagonally (its controls; every qubit of a phase gate)
+    auto acts = [](const PGate &g, uint64_t &nd, uint64_t &d) {
+        nd = d = 0;
+        for (int q : g.targets) (g.kind == PGate::PHASE ? d : nd) |= 1ull << q;
+        for (int q : g.controls) d |= 1ull << q;
+    };
+    // When gate i does not fit the open pass, later gates that commute with
+    // every gate skipped so far still join it.  Two gates commute when on
+    // every qubit they share both act diagonally (both are then sums over the
+    // shared qubits' basis states of operators on disjoint qubits), which
+    // covers disjoint gates, phase gates, and controls.  A skipped gate's
+    // qubits block later gates accordingly; the scan stops once every qubit
+    // is blocked non-diagonally or after a bounded number of gates.
+    const uint64_t all = n >= 64 ? ~0ull : (1ull << n) - 1ull;
+    auto lookahead = [&](size_t i) {
+        uint64_t bnd = 0, bd = 0;
+        auto skip = [&](const PGate &h) {
+            uint64_t nd, d;
+            acts(h, nd, d);
+            bnd |= nd;
+            bd |= d;
+        };
+        skip(pgs[i]);
+        size_t scanned = 0;
+        for (size_t j = i + 1; j < pgs.size() && scanned < PASS_LOOKAHEAD && bnd != all; ++j) {
+            if (done[j]) continue;
+            ++scanned;
+            const PGate &h = pgs[j];
+            uint64_t nd, d;
+            acts(h, nd, d);
+            const bool commutes = !(nd & (bnd | bd)) && !(d & bnd);
+            if (commutes && h.kind != PGate::OTHER && __builtin_popcountll(S | needed(h)) <= L) {
+                S |= needed(h);
+                run.push_back(h);
+                done[j] = 1;
+            } else {
+                skip(h);
+            }
         }
     };
     for (size_t i = 0; i < pgs.size(); ++i) {
-        PGate &g = pgs[i];
-        if (g.kind == PGate::OTHER) {
+        if (done[i]) continue;
+        if (pgs[i].kind == PGate::OTHER) {
+            if (!run.empty()) lookahead(i);
             int st = close();
-            sync_relabel(i);
+            sync_relabel();
+            done[i] = 1;
             if (!st) st = plan_add_gate_op(p, gates[i]);
             if (st) return st;
+            p->ops.back().gate_ids = {circuit_index[i]};
             continue;
         }
-        auto needed = [&]() {
-            uint64_t m = 0;
-            if (g.kind == PGate::NONDIAG || g.kind == PGate::SWAP)
-                for (int q : g.targets) m |= 1ull << q;
-            return m;
-        };
-        if (__builtin_popcountll(S | needed()) > L) {
+        if (__builtin_popcountll(S | needed(pgs[i])) > L) {
+            lookahead(i);
             int st = close();
             if (st) return st;
-            sync_relabel(i);
+            sync_relabel();
         }
-        S |= needed();
-        run.push_back(g);
+        S |= needed(pgs[i]);
+        run.push_back(pgs[i]);
+        done[i] = 1;
     }
     int st = close();
     if (st) return st;
-    if (!moved || folded) return QSV_OK;
+    if (nfolded == pending.size()) return QSV_OK;
     const double s_amp = p->dtype == QSV_C64 ? 8.0 : 16.0;
-    if (involution) {
+    // A permutation sweep per involution left, unless a few SWAPs of
+    // physical qubits do it for less (a SWAP costs about one sweep).
+    if (nfolded == 0 && pending.size() == 2) {
+        if (nswaps <= 2) {
+            std::vector<int> at(n);   // at[b] = logical qubit held by physical bit b
+            for (int q = 0; q < n; ++q) at[phys[q]] = q;
+            for (int b = 0; b < n; ++b) {
+                if (at[b] == b) continue;
+                const int other = phys[b];   // physical bit holding logical qubit b
+                qsv_gate g;
+                std::memset(&g, 0, sizeof(g));
+                g.kind = QSV_GATE_SWAP;
+                g.k = 2;
+                g.targets[0] = b;
+                g.targets[1] = other;
+                if ((st = plan_add_gate_op(p, g))) return st;
+                const int qb = at[b];
+                std::swap(at[b], at[other]);
+                phys[qb] = other;
+                phys[b] = b;
+            }
+            return QSV_OK;
+        }
+    }
+    for (size_t k = nfolded; k < pending.size(); ++k) {
+        const std::vector<int> &t = pending[k];
         PlanOp op;
         op.bytes = 2.0 * std::ldexp(1.0, n) * s_amp;
         // local set: the lowest bits, each with its image, so that both the
         // loads and the stores run over the longest contiguous stretches; a
         // chunk one bit smaller when no closed set of L bits exists
         auto lowest_closed = [&](int size, uint64_t &out) {
-            uint64_t s = 0;
+            uint64_t sl = 0;
             for (int b = 0; b < n; ++b) {
-                if ((s >> b) & 1) continue;
-                const int need = sigma[b] == b ? 1 : 2;
-                if (__builtin_popcountll(s) + need > size) continue;
-                s |= (1ull << b) | (1ull << sigma[b]);
+                if ((sl >> b) & 1) continue;
+                const int need = t[b] == b ? 1 : 2;
+                if (__builtin_popcountll(sl) + need > size) continue;
+                sl |= (1ull << b) | (1ull << t[b]);
             }
-            out = s;
-            return __builtin_popcountll(s) == size && (s & ((1ull << lanes) - 1ull)) == (1ull << lanes) - 1ull;
+            out = sl;
+            return __builtin_popcountll(sl) == size && (sl & ((1ull << lanes) - 1ull)) == (1ull << lanes) - 1ull;
         };
-        // (at most 12 local bits when sigma moves a lane bit, which takes an
-        // LDS exchange: the pass has no gates to amortise, and a 32 KiB chunk
-        // lets several workgroups share a CU, so one's loads overlap
-        // another's exchange and stores; without an exchange the largest
-        // chunk streams best)
+        // (at most 12 local bits when the involution moves a lane bit, which
+        // takes an LDS exchange: the pass has no gates to amortise, and a
+        // 32 KiB chunk lets several workgroups share a CU, so one's loads
+        // overlap another's exchange and stores; without an exchange the
+        // largest chunk streams best)
         bool moves_lanes = false;
         for (int b = 0; b < lanes; ++b)
-            if (sigma[b] != b) moves_lanes = true;
+            if (t[b] != b) moves_lanes = true;
         uint64_t Sp = 0;
         int rbp = -1;
         const int l12 = std::min(L, 12);
@@ -679,42 +782,22 @@ int build_passes_once(qsv_plan *p, int local_bits, bool allow_fold) {
             if (size - TB < 1 || rbp >= 0) continue;
             if (lowest_closed(size, Sp)) rbp = size - TB;
         }
-        const bool closed = rbp >= 1;
-        if (p->opts.jit && closed) {
-            // compiled plans: a pass without gates whose store applies sigma
+        if (p->opts.jit && rbp >= 1) {
+            // compiled plans: a pass without gates whose store applies t
             std::vector<int> local;
             for (int q = 0; q < n; ++q)
                 if ((Sp >> q) & 1) local.push_back(q);
             auto prog = std::make_shared<PassProgram>();
-            int st2 = compile_pass(n, {}, local, rbp, *prog, &sigma);
+            int st2 = compile_pass(n, {}, local, rbp, *prog, &t);
             if (st2) return st2;
             op.kind = PlanOp::PASS;
             op.pass = prog;
         } else {
             op.kind = PlanOp::PERM;
-            op.sigma = sigma;
+            op.sigma = t;
         }
         p->ops.push_back(std::move(op));
         p->stats.n_passes++;
-        return QSV_OK;
-    }
-    // otherwise physical SWAPs, one per misplaced qubit
-    std::vector<int> at(n);   // at[b] = logical qubit held by physical bit b
-    for (int q = 0; q < n; ++q) at[phys[q]] = q;
-    for (int b = 0; b < n; ++b) {
-        if (at[b] == b) continue;
-        const int other = phys[b];   // physical bit holding logical qubit b
-        qsv_gate g;
-        std::memset(&g, 0, sizeof(g));
-        g.kind = QSV_GATE_SWAP;
-        g.k = 2;
-        g.targets[0] = b;
-        g.targets[1] = other;
-        if ((st = plan_add_gate_op(p, g))) return st;
-        const int qb = at[b];
-        std::swap(at[b], at[other]);
-        phys[qb] = other;
-        phys[b] = b;
     }
     return QSV_OK;
 }

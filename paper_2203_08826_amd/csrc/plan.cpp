@@ -181,6 +181,7 @@ int build_greedy(qsv_plan *p, int kmax, bool allow_mfma) {
             if (!st) st = plan_add_block_op(p, qubits, M, allow_mfma);
         }
         if (st) return st;
+        p->ops.back().gate_ids = members;
     }
     return QSV_OK;
 }
@@ -256,8 +257,10 @@ int qsv_plan_create(int n, int dtype, const qsv_gate *gates, int ngates, const q
     }
     switch (o.mode) {
     case QSV_PLAN_PER_GATE:
-        for (const auto &g : p->gates)
-            if ((st = plan_add_gate_op(p.get(), g))) return st;
+        for (size_t i = 0; i < p->gates.size(); ++i) {
+            if ((st = plan_add_gate_op(p.get(), p->gates[i]))) return st;
+            p->ops.back().gate_ids = {(int)i};
+        }
         break;
     case QSV_PLAN_GREEDY: st = build_greedy(p.get(), o.kmax, o.use_mfma != 0); break;
     case QSV_PLAN_PASSES: st = build_passes(p.get(), o.local_bits); break;
@@ -309,6 +312,18 @@ int qsv_plan_op_info(const qsv_plan *plan, int index, int *kind, double *bytes, 
     if (kind) *kind = (int)op.kind;
     if (bytes) *bytes = op.bytes;
     if (flops) *flops = op.flops;
+    return QSV_OK;
+}
+
+int qsv_plan_op_gates(const qsv_plan *plan, int index, int *ids, size_t cap, size_t *count) {
+    if (!plan || !count) return fail(QSV_ERR_NULL, "NULL argument");
+    if (index < 0 || index >= (int)plan->ops.size()) return fail(QSV_ERR_ARG, "op index out of bounds");
+    const std::vector<int> &g = plan->ops[index].gate_ids;
+    *count = g.size();
+    if (ids) {
+        if (cap < g.size()) return fail(QSV_ERR_ARG, "buffer too small");
+        std::copy(g.begin(), g.end(), ids);
+    }
     return QSV_OK;
 }
 

@@ -27,6 +27,7 @@ constexpr int PASS_MAX_THREAD_BITS = 9;
 constexpr int PASS_MAX_RB = 5;
 constexpr int PASS_MAX_L = PASS_MAX_RB + PASS_MAX_THREAD_BITS;
 constexpr int PASS_MAX_SLOTS = 64;       // per op: one per lane of a wave
+constexpr size_t PASS_LOOKAHEAD = 4096;   // gates a pass planner scans past one that does not fit
 constexpr int PASS_SLOT_TERMS = 32;      // longer slots are split
 
 enum PassOpKind : int32_t { POP_EXCHANGE = 1, POP_G1 = 2, POP_G1R = 3, POP_G2 = 4, POP_PHASE = 5 };
@@ -136,6 +137,7 @@ struct PlanOp {
     std::vector<double> matrix;            // MFMA_BLOCK: complex128 4^k
     std::shared_ptr<PassProgram> pass;     // PASS
     bool fused = false;                    // GATE built from a fused block of several gates
+    std::vector<int> gate_ids;             // circuit indices of the gates applied, in application order
     double bytes = 0, flops = 0;
 };
 

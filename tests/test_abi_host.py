@@ -130,3 +130,48 @@ def test_final_permutation_folds_only_when_it_saves_a_sweep():
     assert kinds(qi) == [2, 2, 2, 2, 3]
     qc = qsv.qsv_plan_create(30, qsv.QSV_C64, W.qft(30), mode=qsv.PLAN_PASSES, local_bits=12, jit=1)
     assert kinds(qc) == [2, 2, 2, 2, 2] and qc.stats()["n_jit_passes"] == 5
+
+
+def _no_swaps(circ):
+    return [g for g in circ if not (g["name"] == "SWAP" and not g.get("controls"))]
+
+
+@pytest.mark.parametrize("name,n,jit", [("supremacy", 14, 0), ("variational", 13, 0), ("random", 14, 0), ("random3", 16, 0),
+                                        ("supremacy", 16, 1)])
+def test_pass_planner_reorders_only_commuting_gates(name, n, jit):
+    """The pass planner lets a gate join an open pass ahead of earlier gates
+    it commutes with.  The ops' gate lists form a reordering of the circuit,
+    and the oracle applied in that order gives the circuit's state."""
+    from oracle import statevec as S
+    circ = {"supremacy": lambda: W.supremacy(n, 8, seed=3),
+            "variational": lambda: W.variational(n, 4, seed=3),
+            "random": lambda: _no_swaps(W.random_circuit(n, 300, seed=3, kmax=2, max_controls=1)),
+            "random3": lambda: _no_swaps(W.random_circuit(n, 300, seed=4, kmax=3, max_controls=2))}[name]()
+    p = qsv.qsv_plan_create(n, qsv.QSV_C128, circ, mode=qsv.PLAN_PASSES, local_bits=10 if jit else 9, jit=jit)
+    order = [i for k in range(p.stats()["n_launches"]) for i in qsv.qsv_plan_op_gates(p, k)]
+    assert sorted(order) == list(range(len(circ)))
+    assert order != sorted(order)   # something moved
+    psi0 = W.random_state(n, 7)
+    want = S.run_circuit(psi0, circ)
+    got = S.run_circuit(psi0, [circ[i] for i in order])
+    assert np.max(np.abs(got - want)) <= 1e-12
+
+
+def test_lookahead_respects_non_commuting_gates():
+    """A phase gate may pass a skipped gate only where both act diagonally:
+    Z on q0 passes a skipped CZ(q11, q0) but not a skipped H on q0's partner
+    path; a gate on a skipped gate's target waits."""
+    n = 12
+    circ = [W.gate("H", [q]) for q in range(9)]           # fills the 9 local bits
+    circ += [W.gate("H", [11])]                           # 9: does not fit -> skipped
+    circ += [W.gate("CZ", [0], [11])]                     # 10: diagonal on 11, skipped H is not -> blocked
+    circ += [W.gate("Z", [0])]                            # 11: 0 is diagonal-blocked only -> joins
+    circ += [W.gate("H", [0])]                            # 12: 0 is blocked by the CZ -> waits
+    circ += [W.gate("RZ", [3], [], [0.4]), W.gate("H", [4])]   # 13, 14: untouched qubits -> join
+    p = qsv.qsv_plan_create(n, qsv.QSV_C128, circ, mode=qsv.PLAN_PASSES, local_bits=9)
+    first = qsv.qsv_plan_op_gates(p, 0)
+    assert first == list(range(9)) + [11, 13, 14]
+    from oracle import statevec as S
+    order = [i for k in range(p.stats()["n_launches"]) for i in qsv.qsv_plan_op_gates(p, k)]
+    psi0 = W.random_state(n, 1)
+    assert np.max(np.abs(S.run_circuit(psi0, [circ[i] for i in order]) - S.run_circuit(psi0, circ))) <= 1e-12

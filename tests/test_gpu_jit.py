@@ -161,3 +161,41 @@ def test_jit_folded_pure_permutation_is_exact(gpu, dt):
     got, stats = _run(psi0, circ, dt, mode=qsv.PLAN_PASSES, local_bits=12, jit=1)
     assert stats["n_launches"] == 1, stats
     assert np.array_equal(got, want)
+
+
+def _cycles_circuit(n, with_gates):
+    """SWAPs forming a 5-cycle and a 3-cycle of qubits (not an involution),
+    with gates before, between and after them."""
+    c = [W.gate("H", [q]) for q in range(4)] if with_gates else [W.gate("X", [0]), W.gate("CNOT", [2], [1])]
+    for a, b in [(0, 1), (1, 7), (7, 12), (12, n - 1), (3, 9), (9, 14)]:
+        c.append(W.gate("SWAP", [a, b]))
+        if with_gates:
+            c.append(W.gate("CU1", [a], [b], [0.1 * (a + 1)]))
+    if with_gates:
+        c += [W.gate("RY", [q], [], [0.2 * q]) for q in (0, 7, 9, n - 1)]
+    else:
+        c += [W.gate("X", [7]), W.gate("CNOT", [n - 1], [9])]
+    return c
+
+
+@pytest.mark.parametrize("jit", [0, 1])
+@pytest.mark.parametrize("dt", [qsv.QSV_C64, qsv.QSV_C128])
+def test_final_permutation_as_two_involutions(gpu, jit, dt):
+    """A final relabelling that is not an involution runs as two involution
+    sweeps (or folds into passes), never as a chain of SWAP gates."""
+    n = 17
+    circ = _cycles_circuit(n, True)
+    psi0 = W.random_state(n, 3)
+    want = S.run_circuit(psi0, circ)
+    lb = 12 if jit else 11
+    got, stats = _run(psi0, circ, dt, mode=qsv.PLAN_PASSES, local_bits=lb, jit=jit)
+    assert stats["n_gate_ops"] == 0, stats
+    assert np.max(np.abs(got - want)) <= TOL[dt], stats
+    # and a pure permutation circuit stays bit-exact
+    circ = _cycles_circuit(n, False)
+    psi0 = W.random_state(n, 4)
+    if dt == qsv.QSV_C64:
+        psi0 = psi0.astype(np.complex64).astype(np.complex128)
+    got, stats = _run(psi0, circ, dt, mode=qsv.PLAN_PASSES, local_bits=lb, jit=jit)
+    assert stats["n_gate_ops"] == 0, stats
+    assert np.array_equal(got, S.run_circuit(psi0, circ))
