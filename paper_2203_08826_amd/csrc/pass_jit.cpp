@@ -19,6 +19,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <elf.h>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -30,6 +31,8 @@ namespace qsv {
 
 struct JitModule {
     std::vector<char> code;                 // code object for gfx950
+    std::string source;                     // the kernel source it was compiled from
+    bool prefetch = false;                  // persistent workgroups with a prefetched next chunk
     std::mutex mu;
     struct Loaded {
         hipModule_t mod = nullptr;
@@ -110,10 +113,30 @@ std::string fmt(const char *f, ...) {
 
 uint32_t swz(uint32_t l) { return l ^ (((l >> 4) ^ (l >> 8) ^ (l >> 12)) & 15u); }
 
+// A matrix or phase entry with the rounding residue of an exact 0 or +-1
+// removed (cos and sin of multiples of pi/2 in floating point): such entries
+// then cost no multiplication.  The change is below 2^-50.
+double snap(double v) {
+    if (std::fabs(v) < 0x1p-50) return 0.0;
+    if (std::fabs(v - 1.0) < 0x1p-50) return 1.0;
+    if (std::fabs(v + 1.0) < 0x1p-50) return -1.0;
+    return v;
+}
+
+// 0, 1, 2, 3 when (re, im) is 1, i, -1, -i; -1 otherwise
+int quarter_turn(double re, double im) {
+    if (im == 0.0 && re == 1.0) return 0;
+    if (re == 0.0 && im == 1.0) return 1;
+    if (im == 0.0 && re == -1.0) return 2;
+    if (re == 0.0 && im == -1.0) return 3;
+    return -1;
+}
+
 class Gen {
   public:
-    Gen(const PassProgram &p, int dtype)
-        : P(p), f32(dtype == QSV_C64), NR(1 << p.RB), pool_offset(((const PassHeaderDev *)p.blob.data())->off_pool) {}
+    Gen(const PassProgram &p, int dtype, const JitVariant &v)
+        : P(p), f32(dtype == QSV_C64), NR(1 << p.RB), pool_offset(((const PassHeaderDev *)p.blob.data())->off_pool),
+          share(v.share), PF(v.prefetch && pass_jit_prefetch(p, dtype)) {}
     std::string source();
 
   private:
@@ -124,9 +147,11 @@ class Gen {
     std::string s;
     int uid = 0;
     double scale = 1.0;   // real factor owed by every amplitude of the tile (see gate())
+    const bool share;     // form products of phase factors shared by several amplitudes once
+    const bool PF;        // prefetch the next chunk (persistent workgroups)
 
     void ln(const std::string &x) { s += x, s += '\n'; }
-    double R(double v) const { return f32 ? (double)(float)v : v; }   // value as the kernel's real type holds it
+    double R(double v) const { v = snap(v); return f32 ? (double)(float)v : v; }   // value as the kernel's real type holds it
     std::string lit(double v) const {
         char buf[64];
         if (f32) snprintf(buf, sizeof(buf), "%af", (double)(float)v);
@@ -307,17 +332,56 @@ void Gen::phase(const PassOpDev &op, int sk) {
             }
         }
     }
-    for (int j = 0; j < NR; ++j) {
-        if (sk >= 0 && ((j >> sk) & 1)) continue;
-        const int tj = sk >= 0 ? (j | (1 << sk)) : j;   // the amplitude the factor multiplies
-        double cre = 1.0, cim = 0.0;
+    // f_j = h_j * Fc[j]: a quarter turn Fc[j] is a free rotation; a product
+    // h_j * Fc[j] that several amplitudes take is formed once (a product used
+    // once is applied as two factors: precomputed ones would all be live at
+    // once)
+    auto fc_of = [&](int j, double &cre, double &cim) {
+        cre = 1.0, cim = 0.0;
         if (op.fc >= 0) {
             cre = R(P.pool[op.fc + 2 * j]);
             cim = R(P.pool[op.fc + 2 * j + 1]);
         }
-        const bool c_one = cre == 1.0 && cim == 0.0;
-        if (!h_one[j]) ln(fmt("          v[%d] = cm(v[%d], %s);", tj, tj, h[j].c_str()));
-        if (!c_one) ln(fmt("          v[%d] = cml(v[%d], %s, %s);", tj, tj, lit(cre).c_str(), lit(cim).c_str()));
+    };
+    typedef std::pair<std::string, std::pair<double, double>> Key;
+    std::map<Key, int> uses;
+    for (int j = 0; j < NR; ++j) {
+        if (sk >= 0 && ((j >> sk) & 1)) continue;
+        double cre, cim;
+        fc_of(j, cre, cim);
+        if (!h_one[j] && quarter_turn(cre, cim) < 0) uses[Key(h[j], {cre, cim})]++;
+    }
+    // shared products first, each right before the amplitudes that take it
+    int ng = 0;
+    for (auto &ku : uses) {
+        if (!share || ku.second < 2) continue;
+        const std::string g = fmt("g%d_%d", id, ng++);
+        ln(fmt("          { const C %s = cml(%s, %s, %s);", g.c_str(), ku.first.first.c_str(),
+               lit(ku.first.second.first).c_str(), lit(ku.first.second.second).c_str()));
+        for (int j = 0; j < NR; ++j) {
+            if (sk >= 0 && ((j >> sk) & 1)) continue;
+            double cre, cim;
+            fc_of(j, cre, cim);
+            if (h_one[j] || Key(h[j], {cre, cim}) != ku.first) continue;
+            const int tj = sk >= 0 ? (j | (1 << sk)) : j;
+            ln(fmt("            v[%d] = cm(v[%d], %s);", tj, tj, g.c_str()));
+        }
+        ln("          }");
+    }
+    for (int j = 0; j < NR; ++j) {
+        if (sk >= 0 && ((j >> sk) & 1)) continue;
+        const int tj = sk >= 0 ? (j | (1 << sk)) : j;   // the amplitude the factor multiplies
+        double cre, cim;
+        fc_of(j, cre, cim);
+        const int rot = quarter_turn(cre, cim);
+        const Key key(h[j], {cre, cim});
+        if (share && !h_one[j] && rot < 0 && uses[key] >= 2) {
+            // applied above
+        } else {
+            if (!h_one[j]) ln(fmt("          v[%d] = cm(v[%d], %s);", tj, tj, h[j].c_str()));
+            if (rot > 0) ln(fmt("          v[%d] = rot%d(v[%d]);", tj, rot, tj));
+            else if (rot < 0) ln(fmt("          v[%d] = cml(v[%d], %s, %s);", tj, tj, lit(cre).c_str(), lit(cim).c_str()));
+        }
         // general terms
         std::string e;
         for (int kI = op.gen_b; kI < op.gen_e; ++kI) {
@@ -334,7 +398,6 @@ void Gen::phase(const PassOpDev &op, int sk) {
 std::string Gen::source() {
     const int L = P.L, RB = P.RB;
     const bool pair = !P.pair_sigma.empty();
-    const bool PF = pass_jit_prefetch(P, f32 ? QSV_C64 : QSV_C128);
     bool any_exchange = false;
     for (auto &op : P.ops)
         if (op.kind == POP_EXCHANGE) any_exchange = true;
@@ -349,6 +412,18 @@ std::string Gen::source() {
        "return r; }");
     ln("__device__ __forceinline__ C cml(C a, R re, R im) { C r; r.x = a.x * re - a.y * im; r.y = a.x * im + a.y * re; "
        "return r; }");
+    ln("__device__ __forceinline__ C rot1(C a) { C r; r.x = -a.y; r.y = a.x; return r; }");    // a * i
+    // global accesses as a uniform 64-bit base (scalar registers) plus a
+    // 32-bit per-thread byte offset: one address form of the memory
+    // instruction, no 64-bit vector address arithmetic per access
+    ln("#define GLB __attribute__((address_space(1)))");
+    ln("__device__ __forceinline__ unsigned long long sreg(unsigned long long x) {");
+    ln("    return ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(x >> 32)) << 32) |");
+    ln("           (unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)x); }");
+    ln("__device__ __forceinline__ C ldg(unsigned long long ub, unsigned off) { return *(const GLB C *)((const GLB char *)ub + off); }");
+    ln("__device__ __forceinline__ void stg(unsigned long long ub, unsigned off, C v) { *(GLB C *)((GLB char *)ub + off) = v; }");
+    ln("__device__ __forceinline__ C rot2(C a) { C r; r.x = -a.x; r.y = -a.y; return r; }");   // a * -1
+    ln("__device__ __forceinline__ C rot3(C a) { C r; r.x = a.y; r.y = -a.x; return r; }");    // a * -i
     if (f32) {
         ln("__device__ __forceinline__ C expi(unsigned long long ph) {");
         ln("    const float x = (float)(int)(unsigned)(ph >> 32) * 2.3283064365386963e-10f;");
@@ -411,13 +486,37 @@ std::string Gen::source() {
             if ((j >> i) & 1) o |= 1ull << pos[part.reg_l[i]];
         return o;
     };
-    std::string ld = "    auto load_chunk = [&](C *dst, unsigned long long b) { const C *p = psi + (b | lt_in);";
-    for (int j = 0; j < NR; ++j) ld += fmt(" dst[%d] = p[%s];", j, u64(reg_off(P.parts[P.load_part], in_pos, j)).c_str());
+    // (per-thread byte offsets below 4 GiB: uniform base + 32-bit offset)
+    const int csz = f32 ? 8 : 16;
+    auto small_offsets = [&](const PassPartition &part, const int *pos) {
+        int top = 0;
+        for (int u = 0; u < P.TB; ++u) top = std::max(top, pos[part.thr_l[u]]);
+        return std::ldexp(1.0, top + 1) * csz <= 4294967296.0;
+    };
+    std::string ld = "    auto load_chunk = [&](C *dst, unsigned long long b) {";
+    if (small_offsets(P.parts[P.load_part], in_pos)) {
+        ln("    const unsigned to_in = (unsigned)(lt_in * sizeof(C));");
+        ld += " const unsigned long long q = (unsigned long long)(psi + b);";
+        for (int j = 0; j < NR; ++j)
+            ld += fmt(" dst[%d] = ldg(sreg(q + %s), to_in);", j,
+                      u64(reg_off(P.parts[P.load_part], in_pos, j) * csz).c_str());
+    } else {
+        ld += " const C *p = psi + (b | lt_in);";
+        for (int j = 0; j < NR; ++j) ld += fmt(" dst[%d] = p[%s];", j, u64(reg_off(P.parts[P.load_part], in_pos, j)).c_str());
+    }
     ld += " };";
     ln(ld);
-    std::string sto = "    auto store_chunk = [&](const C *src, unsigned long long b) { C *p = psi + (b | lt_out);";
-    for (int j = 0; j < NR; ++j)
-        sto += fmt(" p[%s] = src[%d];", u64(reg_off(P.parts[final_part], out_pos, j)).c_str(), j);
+    std::string sto = "    auto store_chunk = [&](const C *src, unsigned long long b) {";
+    if (small_offsets(P.parts[final_part], out_pos)) {
+        ln("    const unsigned to_out = (unsigned)(lt_out * sizeof(C));");
+        sto += " const unsigned long long q = (unsigned long long)(psi + b);";
+        for (int j = 0; j < NR; ++j)
+            sto += fmt(" stg(sreg(q + %s), to_out, src[%d]);", u64(reg_off(P.parts[final_part], out_pos, j) * csz).c_str(), j);
+    } else {
+        sto += " C *p = psi + (b | lt_out);";
+        for (int j = 0; j < NR; ++j)
+            sto += fmt(" p[%s] = src[%d];", u64(reg_off(P.parts[final_part], out_pos, j)).c_str(), j);
+    }
     sto += " };";
     ln(sto);
     if (pair) {
@@ -582,9 +681,87 @@ int compile_source(const std::string &src, std::vector<char> &code, std::string 
 
 }  // namespace
 
-std::string pass_jit_source(const PassProgram &prog, int dtype) {
-    Gen g(prog, dtype);
+std::string pass_jit_source(const PassProgram &prog, int dtype, const JitVariant &v) {
+    Gen g(prog, dtype, v);
     return g.source();
+}
+
+std::string pass_jit_module_source(const PassProgram &prog) { return prog.jit ? prog.jit->source : std::string(); }
+
+namespace {
+
+// Bytes of scratch (private segment) per lane that the kernel descriptor of
+// `kernel` requests in an AMDGPU ELF code object; -1 when it is not found.
+long kernel_scratch_bytes(const std::vector<char> &co, const std::string &kernel) {
+    const size_t n = co.size();
+    if (n < sizeof(Elf64_Ehdr) || std::memcmp(co.data(), ELFMAG, SELFMAG) != 0) return -1;
+    Elf64_Ehdr eh;
+    std::memcpy(&eh, co.data(), sizeof(eh));
+    if (eh.e_shentsize != sizeof(Elf64_Shdr) || eh.e_shoff > n || eh.e_shnum > (n - eh.e_shoff) / sizeof(Elf64_Shdr))
+        return -1;
+    std::vector<Elf64_Shdr> sh(eh.e_shnum);
+    if (eh.e_shnum) std::memcpy(sh.data(), co.data() + eh.e_shoff, eh.e_shnum * sizeof(Elf64_Shdr));
+    const std::string kd = kernel + ".kd";
+    for (const auto &tab : sh) {
+        if (tab.sh_type != SHT_SYMTAB && tab.sh_type != SHT_DYNSYM) continue;
+        if (tab.sh_link >= sh.size() || tab.sh_offset > n || tab.sh_size > n - tab.sh_offset) continue;
+        const Elf64_Shdr &str = sh[tab.sh_link];
+        if (str.sh_offset > n || str.sh_size > n - str.sh_offset) continue;
+        for (size_t k = 0; k + 1 <= tab.sh_size / sizeof(Elf64_Sym); ++k) {
+            Elf64_Sym sym;
+            std::memcpy(&sym, co.data() + tab.sh_offset + k * sizeof(Elf64_Sym), sizeof(sym));
+            if (sym.st_name >= str.sh_size) continue;
+            const char *nm = co.data() + str.sh_offset + sym.st_name;
+            if (strnlen(nm, str.sh_size - sym.st_name) != kd.size() || kd.compare(0, kd.size(), nm, kd.size()) != 0)
+                continue;
+            if (sym.st_shndx >= sh.size()) return -1;
+            const Elf64_Shdr &sec = sh[sym.st_shndx];
+            if (sym.st_value < sec.sh_addr) return -1;
+            const uint64_t off = sec.sh_offset + (sym.st_value - sec.sh_addr);
+            if (off > n || n - off < 8) return -1;
+            uint32_t priv = 0;   // kernel descriptor: group segment size, then private segment size
+            std::memcpy(&priv, co.data() + off + 4, 4);
+            return (long)priv;
+        }
+    }
+    return -1;
+}
+
+}  // namespace
+
+// Compiles a pass, first as `first` (the default variant's source).  A
+// kernel whose registers spill to scratch is compiled again without shared
+// phase products, then without the prefetched chunk, then without both
+// (each frees registers).  A prefetching variant is kept if it spills at
+// most a few values (measured: cheaper than giving up the prefetch); else
+// the first variant without scratch, else the one with the least.
+std::shared_ptr<JitModule> compile_pass_kernel(const PassProgram &prog, int dtype, const std::string &first,
+                                               std::string &err) {
+    const JitVariant vs[4] = {{true, true}, {false, true}, {true, false}, {false, false}};
+    constexpr long SMALL_SPILL = 16;   // bytes per lane
+    std::shared_ptr<JitModule> best;
+    long best_scratch = -1;
+    std::vector<std::string> tried;
+    for (int vi = 0; vi < 4; ++vi) {
+        const JitVariant &v = vs[vi];
+        if (vi == 2 && best && best->prefetch && best_scratch >= 0 && best_scratch <= SMALL_SPILL) break;
+        std::string src = tried.empty() ? first : pass_jit_source(prog, dtype, v);
+        bool seen = false;
+        for (auto &t : tried) seen = seen || t == src;
+        if (seen) continue;
+        tried.push_back(src);
+        auto m = std::make_shared<JitModule>();
+        if (compile_source(src, m->code, err)) return best;
+        const long sc = kernel_scratch_bytes(m->code, JIT_KERNEL_NAME);
+        m->source.swap(src);
+        m->prefetch = v.prefetch && pass_jit_prefetch(prog, dtype);
+        if (!best || (sc >= 0 && (best_scratch < 0 || sc < best_scratch))) {
+            best = m;
+            best_scratch = sc;
+        }
+        if (sc == 0) break;
+    }
+    return best;
 }
 
 int jit_compile_plan(qsv_plan *p) {
@@ -598,7 +775,7 @@ int jit_compile_plan(qsv_plan *p) {
     {
         std::lock_guard<std::mutex> lk(cache_mu);
         for (size_t i = 0; i < progs.size(); ++i) {
-            srcs[i] = pass_jit_source(*progs[i], p->dtype);
+            srcs[i] = pass_jit_source(*progs[i], p->dtype, JitVariant());
             auto it = cache.find(srcs[i]);
             if (it != cache.end()) mods[i] = it->second;
             else todo.push_back(i);
@@ -610,7 +787,7 @@ int jit_compile_plan(qsv_plan *p) {
     for (size_t i : todo)
         if (first.emplace(srcs[i], i).second) uniq.push_back(i);
     std::vector<std::string> errs(uniq.size());
-    std::vector<std::vector<char>> codes(uniq.size());
+    std::vector<std::shared_ptr<JitModule>> built(uniq.size());
     size_t nth = std::max<size_t>(1, std::min<size_t>(uniq.size(), std::min(16u, std::max(1u, std::thread::hardware_concurrency()))));
     std::vector<std::thread> th;
     std::mutex next_mu;
@@ -624,20 +801,16 @@ int jit_compile_plan(qsv_plan *p) {
                     if (next >= uniq.size()) return;
                     u = next++;
                 }
-                if (compile_source(srcs[uniq[u]], codes[u], errs[u])) codes[u].clear();
+                built[u] = compile_pass_kernel(*progs[uniq[u]], p->dtype, srcs[uniq[u]], errs[u]);
             }
         });
     for (auto &x : th) x.join();
     for (size_t u = 0; u < uniq.size(); ++u)
-        if (codes[u].empty()) return fail(QSV_ERR_UNSUPPORTED, "pass kernel compilation failed: " + errs[u]);
+        if (!built[u]) return fail(QSV_ERR_UNSUPPORTED, "pass kernel compilation failed: " + errs[u]);
     {
         std::lock_guard<std::mutex> lk(cache_mu);
         if (cache.size() + uniq.size() > CACHE_MAX) cache.clear();   // plans keep their own modules
-        for (size_t u = 0; u < uniq.size(); ++u) {
-            auto m = std::make_shared<JitModule>();
-            m->code.swap(codes[u]);
-            cache[srcs[uniq[u]]] = m;
-        }
+        for (size_t u = 0; u < uniq.size(); ++u) cache[srcs[uniq[u]]] = built[u];
         for (size_t i : todo) mods[i] = cache[srcs[i]];
     }
     for (size_t i = 0; i < progs.size(); ++i) progs[i]->jit = mods[i];
@@ -676,7 +849,7 @@ int launch_pass_jit(void *state, int n, int dtype, const PassProgram &prog, hipS
     int st = upload_pass_program(prog, dtype, s, &slot);
     if (st) return st;
     uint64_t nchunks = 1ull << (n - prog.L);
-    const bool pf = pass_jit_prefetch(prog, dtype);
+    const bool pf = jm.prefetch;
     uint64_t g = pf ? (uint64_t)per_cu * device_sm_count() : std::min<uint64_t>(nchunks, 1ull << 20);
     if (g > nchunks) g = nchunks;
     void *dprog = slot.dev;

@@ -348,7 +348,8 @@ int qsv_plan_op_source(const qsv_plan *plan, int index, char *buf, size_t cap, s
     if (index < 0 || index >= (int)plan->ops.size()) return fail(QSV_ERR_ARG, "op index out of bounds");
     const PlanOp &op = plan->ops[index];
     if (op.kind != PlanOp::PASS) return fail(QSV_ERR_ARG, "op is not an LDS pass");
-    const std::string src = pass_jit_source(*op.pass, plan->dtype);
+    const std::string src = op.pass->jit ? pass_jit_module_source(*op.pass)
+                                         : pass_jit_source(*op.pass, plan->dtype, JitVariant());
     *size = src.size() + 1;
     if (buf) {
         if (cap < src.size() + 1) return fail(QSV_ERR_ARG, "buffer too small");

@@ -122,7 +122,15 @@ struct PassProgram {
 int upload_pass_program(const PassProgram &prog, int dtype, hipStream_t s, StagingSlot *slot);
 int launch_pass_program(void *state, int n, int dtype, const PassProgram &prog, hipStream_t s);
 int launch_pass_jit(void *state, int n, int dtype, const PassProgram &prog, hipStream_t s);
-std::string pass_jit_source(const PassProgram &prog, int dtype);
+// Code-generation choices of a compiled pass: products of phase factors
+// that several amplitudes take formed once (fewer multiplications, more live
+// registers); the next chunk prefetched into registers where that applies.
+struct JitVariant {
+    bool share = true;
+    bool prefetch = true;
+};
+std::string pass_jit_source(const PassProgram &prog, int dtype, const JitVariant &v);
+std::string pass_jit_module_source(const PassProgram &prog);   // the source of the kernel compiled, if any
 std::vector<int> pair_chunk_order(const std::vector<int> &sigma, uint64_t local);
 bool pass_jit_prefetch(const PassProgram &p, int dtype);
 int launch_bitperm(void *state, int n, int dtype, const std::vector<int> &sigma, hipStream_t s);
