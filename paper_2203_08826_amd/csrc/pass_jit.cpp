@@ -64,6 +64,29 @@ bool pass_jit_prefetch(const PassProgram &p, int dtype) {
     return dtype == QSV_C64 ? p.RB <= 4 : p.RB <= 3;
 }
 
+// Non-local bits of a chunk-pair pass: the pairs (a, b) that sigma swaps
+// (a < b, ascending a) and the bits it fixes.
+PairLayout pair_layout(const std::vector<int> &sigma, uint64_t local) {
+    PairLayout pl;
+    for (int q = 0; q < (int)sigma.size(); ++q) {
+        if ((local >> q) & 1) continue;
+        if (sigma[q] == q) pl.fixed.push_back(q);
+        else if (sigma[q] > q) {
+            pl.a.push_back(q);
+            pl.b.push_back(sigma[q]);
+        }
+    }
+    return pl;
+}
+
+// Work items of a chunk-pair pass: one per pair {c, sigma(c)} of distinct
+// chunks and one per chunk sigma fixes, (4^m + 2^m) 2^f / 2 in all.
+uint64_t pair_work_items(const std::vector<int> &sigma, uint64_t local) {
+    const PairLayout pl = pair_layout(sigma, local);
+    const int m = (int)pl.a.size(), f = (int)pl.fixed.size();
+    return ((1ull << (2 * m + f)) + (1ull << (m + f))) / 2;
+}
+
 // Enumeration order of the non-local bits (mask ~local over sigma's bits)
 // for chunk-pair work: the lowest K non-local bits, then their images under
 // sigma, then the rest ascending.
@@ -524,14 +547,30 @@ std::string Gen::source() {
         const int n = (int)P.pair_sigma.size();
         uint64_t local = 0, fixed = 0;
         for (int l = 0; l < L; ++l) local |= 1ull << P.local_sorted[l];
-        // Work item w -> chunk base: the lowest bits of w go to the lowest
-        // non-local bits and to their images under sigma, so the workgroups
-        // running at the same time cover contiguous runs of chunks on both
-        // sides of their pairs.
-        const std::vector<int> order = pair_chunk_order(P.pair_sigma, local);
-        std::string cbw = "    auto pair_base = [&](unsigned long long w) { return 0ull";
-        for (size_t j = 0; j < order.size(); ++j) cbw += fmt(" | (((w >> %zu) & 1ull) << %d)", j, order[j]);
-        cbw += "; };";
+        // Work item w -> chunk base, one item per pair {c, sigma(c)} (see
+        // pair_work_items): groups k = 0..m-1 take the chunks whose first
+        // differing pair (ascending a) is pair k, with a_k = 1 and b_k = 0;
+        // group m the chunks sigma fixes.  Within a group the bits of w go
+        // to the a-bits of the free pairs first (neighbouring chunks), then
+        // their b-bits, the fixed bits and the equal pairs.
+        const PairLayout pl = pair_layout(P.pair_sigma, local);
+        const int m = (int)pl.a.size(), f = (int)pl.fixed.size();
+        std::string cbw = "    auto pair_base = [&](unsigned long long w) {";
+        uint64_t start = 0;
+        for (int k = 0; k <= m; ++k) {
+            const uint64_t size = k < m ? (1ull << (k + 2 * (m - 1 - k) + f)) : (1ull << (m + f));
+            std::string e = k < m ? u64(1ull << pl.a[k]) : std::string("0ull");
+            int i = 0;
+            for (int j = k + 1; j < m; ++j, ++i) e += fmt(" | (((r >> %d) & 1ull) << %d)", i, pl.a[j]);
+            for (int j = k + 1; j < m; ++j, ++i) e += fmt(" | (((r >> %d) & 1ull) << %d)", i, pl.b[j]);
+            for (int j = 0; j < f; ++j, ++i) e += fmt(" | (((r >> %d) & 1ull) << %d)", i, pl.fixed[j]);
+            for (int j = 0; j < k && j < m; ++j, ++i)
+                e += fmt(" | (((r >> %d) & 1ull) * %s)", i, u64((1ull << pl.a[j]) | (1ull << pl.b[j])).c_str());
+            cbw += fmt(" if (w < %s) { const unsigned long long r = w - %s; (void)r; return %s; }",
+                       u64(start + size).c_str(), u64(start).c_str(), e.c_str());
+            start += size;
+        }
+        cbw += " return 0ull; };";
         ln(cbw);
         std::string e = "    auto partner = [&](unsigned long long b) { return (b & ";
         for (int q = 0; q < n; ++q)
@@ -607,7 +646,6 @@ std::string Gen::source() {
         // chunk pairs (c, sigma(c)), moved by the workgroup of the smaller base;
         // every load of both tiles completes before the first store (in place)
         ln("        const unsigned long long pbase = partner(base);");
-        ln("        if (pbase < base) continue;");
         ln("        const bool pr = pbase != base;");
         ln(fmt("        C w[%d];", NR));
         ln("        load_chunk(v, base);");
@@ -849,6 +887,11 @@ int launch_pass_jit(void *state, int n, int dtype, const PassProgram &prog, hipS
     int st = upload_pass_program(prog, dtype, s, &slot);
     if (st) return st;
     uint64_t nchunks = 1ull << (n - prog.L);
+    if (!prog.pair_sigma.empty()) {
+        uint64_t local = 0;
+        for (int q : prog.local_sorted) local |= 1ull << q;
+        nchunks = pair_work_items(prog.pair_sigma, local);
+    }
     const bool pf = jm.prefetch;
     uint64_t g = pf ? (uint64_t)per_cu * device_sm_count() : std::min<uint64_t>(nchunks, 1ull << 20);
     if (g > nchunks) g = nchunks;

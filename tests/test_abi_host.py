@@ -175,3 +175,50 @@ def test_lookahead_respects_non_commuting_gates():
     order = [i for k in range(p.stats()["n_launches"]) for i in qsv.qsv_plan_op_gates(p, k)]
     psi0 = W.random_state(n, 1)
     assert np.max(np.abs(S.run_circuit(psi0, [circ[i] for i in order]) - S.run_circuit(psi0, circ))) <= 1e-12
+
+
+def _lambda_body(src, head, tail):
+    i = src.index(head) + len(head)
+    return src[i:src.index(tail, i)]
+
+
+def _c_expr(e):
+    return re.sub(r"(0x[0-9a-f]+|\d+)ull", r"\1", e)
+
+
+@pytest.mark.parametrize("n,circ_kind", [(16, "reversal"), (17, "mixed")])
+def test_chunk_pair_enumeration_covers_each_pair_once(n, circ_kind):
+    """A compiled pass that stores its result permuted pairs chunk c with
+    chunk sigma(c); its work items enumerate one representative per pair
+    (and every chunk sigma fixes), which the generated index maps must
+    cover exactly once."""
+    if circ_kind == "reversal":
+        circ = [W.gate("H", [0])] + [W.gate("SWAP", [i, n - 1 - i]) for i in range(n // 2)]
+    else:   # some non-local bits fixed, some paired
+        circ = [W.gate("H", [0])] + [W.gate("SWAP", [a, b]) for a, b in [(0, 15), (1, 14), (12, 16), (3, 4)]]
+    p = qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_PASSES, local_bits=12, jit=1)
+    src = [qsv.qsv_plan_op_source(p, k) for k in range(p.stats()["n_launches"])]
+    src = [s for s in src if "pair_base" in s]
+    assert src, "no chunk-pair pass"
+    s = src[0]
+    body = _lambda_body(s, "auto pair_base = [&](unsigned long long w) {", " return 0ull; };")
+    groups = re.findall(r"if \(w < (\w+)\) \{ const unsigned long long r = w - (\w+); \(void\)r; return ([^;]+); \}", body)
+    groups = [(int(_c_expr(a), 0), int(_c_expr(b), 0), _c_expr(e)) for a, b, e in groups]
+    part = _c_expr(_lambda_body(s, "auto partner = [&](unsigned long long b) { return ", "; };"))
+    partner = eval("lambda b: " + part)
+    items = groups[-1][0]
+    seen = set()
+    for w in range(items):
+        for end, start, e in groups:
+            if w < end:
+                base = eval(e, {"r": w - start})
+                break
+        pb = partner(base)
+        assert partner(pb) == base
+        key = (min(base, pb), max(base, pb))
+        assert key not in seen, (w, base, pb)
+        seen.add(key)
+    # every chunk appears in exactly one pair: 2 * pairs + fixed = chunks
+    chunks = {b for k in seen for b in k}
+    L = 12
+    assert len(chunks) == 1 << (n - L)
