@@ -169,7 +169,7 @@ class Gen {
     const int pool_offset;   // byte offset of the real pool in the serialised program
     std::string s;
     int uid = 0;
-    double scale = 1.0;   // real factor owed by every amplitude of the tile (see gate())
+    double scale_re = 1.0, scale_im = 0.0;   // complex factor owed by every amplitude of the tile (see gate())
     const bool share;     // form products of phase factors shared by several amplitudes once
     const bool PF;        // prefetch the next chunk (persistent workgroups)
 
@@ -228,27 +228,52 @@ std::string Gen::thread_offset(const PassPartition &part, const int *pos, bool g
 void Gen::gate(const PassOpDev &op, const std::vector<int> &bits, const std::vector<double> &M0, bool real) {
     const int k = (int)bits.size(), d = 1 << k;
     const bool tok = op.ct != 0 || op.cn != 0;
-    // An uncontrolled gate whose nonzero entries all have one magnitude m
-    // (H, the square roots of X and Y, ...) acts on every amplitude of the
-    // tile, so m can be factored out: the gate's skeleton M / m (entries of
-    // modulus 1, often +-1 and +-i: additions only) runs here and m joins the
-    // real factor that the pass applies once before its store (every op of a
-    // pass is linear, so the factor commutes with the rest).
+    // An uncontrolled gate acts on every amplitude of the tile, so a common
+    // factor c of its entries can be taken out: the gate's skeleton M / c
+    // runs here and c joins the factor that the pass applies once before its
+    // store (every op of a pass is linear, so the factor commutes with the
+    // rest).  c is the first nonzero entry when every entry is c times one of
+    // 0, +-1, +-i (the square roots of X and Y: additions only), else the
+    // common magnitude when all nonzero entries share one (H, ...).
     std::vector<double> M = M0;
     if (!tok && op.cj == 0) {
-        double mag = -1.0;
-        bool same = true;
         const int ne = d * d;
-        for (int e = 0; e < ne && same; ++e) {
-            const double re = real ? M[e] : M[2 * e], im = real ? 0.0 : M[2 * e + 1];
+        auto entry = [&](int e, double &re, double &im) {
+            re = real ? M[e] : M[2 * e];
+            im = real ? 0.0 : M[2 * e + 1];
+        };
+        double cre = 0.0, cim = 0.0, mag = -1.0;
+        bool quarter = true, same = true;
+        for (int e = 0; e < ne; ++e) {
+            double re, im;
+            entry(e, re, im);
             const double a = std::hypot(re, im);
             if (a == 0.0) continue;
-            if (mag < 0) mag = a;
-            else if (std::fabs(a - mag) > 1e-15 * mag) same = false;
+            if (mag < 0) {
+                mag = a;
+                cre = re;
+                cim = im;
+                continue;
+            }
+            if (std::fabs(a - mag) > 1e-15 * mag) same = false;
+            // e / c = e * conj(c) / |c|^2 must be one of +-1, +-i
+            const double qr = (re * cre + im * cim) / (mag * mag), qi = (im * cre - re * cim) / (mag * mag);
+            if (quarter_turn(snap(qr), snap(qi)) < 0) quarter = false;
         }
-        if (same && mag > 0 && mag != 1.0) {
+        if (mag > 0 && same && quarter && !real && (cre != 1.0 || cim != 0.0)) {
+            const double n2 = cre * cre + cim * cim;
+            for (int e = 0; e < ne; ++e) {
+                const double re = M[2 * e], im = M[2 * e + 1];
+                M[2 * e] = (re * cre + im * cim) / n2;
+                M[2 * e + 1] = (im * cre - re * cim) / n2;
+            }
+            const double sr = scale_re * cre - scale_im * cim, si = scale_re * cim + scale_im * cre;
+            scale_re = sr;
+            scale_im = si;
+        } else if (mag > 0 && same && mag != 1.0) {
             for (double &x : M) x /= mag;
-            scale *= mag;
+            scale_re *= mag;
+            scale_im *= mag;
         }
     }
     if (tok) ln(fmt("        { const bool tk = ((t & %uu) == %uu) && ((base & %s) == %s);", op.ct, op.ct,
@@ -631,7 +656,13 @@ std::string Gen::source() {
         default: break;
         }
     }
-    if (scale != 1.0) {
+    if (snap(scale_im) != 0.0) {
+        std::string e = "        {";
+        for (int j = 0; j < NR; ++j)
+            e += fmt(" v[%d] = cml(v[%d], %s, %s);", j, j, lit(scale_re).c_str(), lit(scale_im).c_str());
+        ln(e + " }");
+    } else if (scale_re != 1.0) {
+        const double scale = scale_re;
         std::string e = "        {";
         for (int j = 0; j < NR; ++j) e += fmt(" v[%d].x *= %s; v[%d].y *= %s;", j, lit(scale).c_str(), j, lit(scale).c_str());
         ln(e + " }");
