@@ -87,34 +87,6 @@ uint64_t pair_work_items(const std::vector<int> &sigma, uint64_t local) {
     return ((1ull << (2 * m + f)) + (1ull << (m + f))) / 2;
 }
 
-// Enumeration order of the non-local bits (mask ~local over sigma's bits)
-// for chunk-pair work: the lowest K non-local bits, then their images under
-// sigma, then the rest ascending.
-std::vector<int> pair_chunk_order(const std::vector<int> &sigma, uint64_t local) {
-    const int n = (int)sigma.size();
-    constexpr int K = 5;
-    std::vector<int> order, rest;
-    std::vector<int> used(n, 0);
-    int low = 0;
-    for (int b = 0; b < n && low < K; ++b)
-        if (!((local >> b) & 1)) {
-            order.push_back(b);
-            used[b] = 1;
-            ++low;
-        }
-    const size_t nlow = order.size();
-    for (size_t i = 0; i < nlow; ++i) {
-        const int p = sigma[order[i]];
-        if (!used[p]) {
-            order.push_back(p);
-            used[p] = 1;
-        }
-    }
-    for (int b = 0; b < n; ++b)
-        if (!((local >> b) & 1) && !used[b]) order.push_back(b);
-    return order;
-}
-
 namespace {
 
 const char *JIT_KERNEL_NAME = "qsv_pass_jit";

@@ -20,11 +20,36 @@ struct BitPermArgs {
     int32_t lpos[BP_MAX_L];        // global bit of local position l
     int32_t lperm[BP_MAX_L];       // local position l -> local position of sigma(bit)
     int32_t gperm[QSV_MAX_QUBITS]; // global bit b -> sigma(b)
-    int32_t order[QSV_MAX_QUBITS]; // work-item bit j -> non-local global bit
+    int32_t pa[QSV_MAX_QUBITS];    // non-local pairs (pa[i], pb[i]) that sigma swaps, ascending pa
+    int32_t pb[QSV_MAX_QUBITS];
+    int32_t fx[QSV_MAX_QUBITS];    // non-local bits sigma fixes
+    int32_t m, f;
     int32_t L;
     int32_t n;
-    uint64_t nchunks;
+    uint64_t nitems;               // one work item per chunk pair {c, sigma(c)}
 };
+
+// Work item -> the chunk base of one representative per pair {c, sigma(c)}:
+// group k < m holds the chunks whose first differing pair is pair k, with
+// bit pa[k] set and pb[k] clear; group m the chunks sigma fixes.  Within a
+// group the item's bits go to the pa-bits of the later pairs (neighbouring
+// chunks), then their pb-bits, the fixed bits and the equal earlier pairs.
+__device__ __forceinline__ uint64_t bp_item_base(uint64_t w, const BitPermArgs &a) {
+    int k = 0;
+    for (; k < a.m; ++k) {
+        const uint64_t size = 1ull << (k + 2 * (a.m - 1 - k) + a.f);
+        if (w < size) break;
+        w -= size;
+    }
+    uint64_t b = k < a.m ? 1ull << a.pa[k] : 0ull;
+    int i = 0;
+    for (int j = k + 1; j < a.m; ++j, ++i) b |= ((w >> i) & 1ull) << a.pa[j];
+    for (int j = k + 1; j < a.m; ++j, ++i) b |= ((w >> i) & 1ull) << a.pb[j];
+    for (int j = 0; j < a.f; ++j, ++i) b |= ((w >> i) & 1ull) << a.fx[j];
+    for (int j = 0; j < k; ++j, ++i)
+        if ((w >> i) & 1ull) b |= (1ull << a.pa[j]) | (1ull << a.pb[j]);
+    return b;
+}
 
 __device__ __forceinline__ uint32_t bp_swz(uint32_t l) { return l ^ (((l >> 4) ^ (l >> 8)) & 15u); }
 
@@ -77,17 +102,11 @@ __global__ void __launch_bounds__(BP_THREADS) k_bitperm(BpC<R> *__restrict__ psi
     __syncthreads();
     // One work item per workgroup (a one-shot grid: the hardware starts the
     // next workgroups while earlier ones store, which keeps loads and stores
-    // overlapped).  Item w is the chunk whose non-local bits are w's bits in
-    // the order a.order (the lowest non-local bits and their images under
-    // sigma vary fastest, so neighbouring workgroups read contiguous runs on
-    // both sides of their pairs).  The workgroup of the smaller base of a pair
-    // moves both; the other one exits at once.
-    const int nn = a.n - L;
-    for (uint64_t w = blockIdx.x; w < a.nchunks; w += gridDim.x) {
-        uint64_t base = 0;
-        for (int j = 0; j < nn; ++j) base |= ((w >> j) & 1ull) << a.order[j];
+    // overlapped); each item is one pair of chunks (or a chunk sigma fixes),
+    // which its workgroup moves whole.
+    for (uint64_t w = blockIdx.x; w < a.nitems; w += gridDim.x) {
+        const uint64_t base = bp_item_base(w, a);
         const uint64_t pbase = bp_permute_global(base, a);   // non-local bits only (local set is closed)
-        if (pbase < base) continue;   // uniform: the partner's item moves this pair
         const bool pair = pbase != base;
         // Both chunks are loaded before anything is stored; each thread writes
         // its loaded values to LDS before the barrier that precedes the first
@@ -190,16 +209,22 @@ int launch_bitperm(void *state, int n, int dtype, const std::vector<int> &sigma,
     {
         uint64_t lm = 0;
         for (int i = 0; i < L; ++i) lm |= 1ull << a.lpos[i];
-        const std::vector<int> order = pair_chunk_order(sigma, lm);
-        for (size_t j = 0; j < order.size(); ++j) a.order[j] = order[j];
+        const PairLayout pl = pair_layout(sigma, lm);
+        a.m = (int)pl.a.size();
+        a.f = (int)pl.fixed.size();
+        for (int i = 0; i < a.m; ++i) {
+            a.pa[i] = pl.a[i];
+            a.pb[i] = pl.b[i];
+        }
+        for (int i = 0; i < a.f; ++i) a.fx[i] = pl.fixed[i];
+        a.nitems = pair_work_items(sigma, lm);
     }
     for (int i = 0; i < L; ++i) {
         const int dst = sigma[a.lpos[i]];
         for (int k = 0; k < L; ++k)
             if (a.lpos[k] == dst) a.lperm[i] = k;
     }
-    a.nchunks = 1ull << (n - L);
-    const unsigned grid = (unsigned)std::min<uint64_t>(a.nchunks, 0x7fffffffull);
+    const unsigned grid = (unsigned)std::min<uint64_t>(a.nitems, 0x7fffffffull);
     if (dtype == QSV_C64)
         hipLaunchKernelGGL(k_bitperm<float>, dim3(grid), dim3(BP_THREADS), 0, s, (BpC<float> *)state, a);
     else

@@ -131,7 +131,6 @@ struct JitVariant {
 };
 std::string pass_jit_source(const PassProgram &prog, int dtype, const JitVariant &v);
 std::string pass_jit_module_source(const PassProgram &prog);   // the source of the kernel compiled, if any
-std::vector<int> pair_chunk_order(const std::vector<int> &sigma, uint64_t local);
 struct PairLayout {
     std::vector<int> a, b;       // the non-local pairs sigma swaps, a < b, ascending a
     std::vector<int> fixed;      // the non-local bits sigma fixes
