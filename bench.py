@@ -125,12 +125,23 @@ def workload_variational(args):
     torch.cuda.synchronize()
     t_ref = time.perf_counter() - t0
     infid = _infidelity(qsv, b, a)
+    # the same circuit as compiled LDS passes (c64)
+    t0 = time.perf_counter()
+    cp = qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_PASSES, jit=1)
+    t_cp_create = time.perf_counter() - t0
+    c = _zero_state(n, torch.complex64)
+    qsv.qsv_plan_execute(cp, c)
+    torch.cuda.synchronize()
+    infid_cp = _infidelity(qsv, b, c)
+    t_cp = _timed(lambda: qsv.qsv_plan_execute(cp, c), 1)
     print(json.dumps({"metric": "circuit s, TFLOP/s, infidelity vs c128", "config": {
         "workload": "variational n=%d layers=%d (%d gates), greedy kmax=5 on FP32 MFMA" % (n, args.layers, len(circ))},
         "fused_c64_s": round(t_fused, 4), "blocks": fs["n_blocks"], "mfma_blocks": fs["n_mfma_blocks"],
         "launches": fs["n_launches"], "GB/s": round(fs["bytes"] / t_fused / 1e9, 1),
         "TFLOP/s": round(fs["flops"] / t_fused / 1e12, 2), "reference_c128_passes_s": round(t_ref, 4),
-        "infidelity_c64_vs_c128": infid}), flush=True)
+        "infidelity_c64_vs_c128": infid,
+        "passes_compiled_c64": {"s": round(t_cp, 4), "launches": cp.stats()["n_launches"],
+                                "plan_create_s": round(t_cp_create, 2), "infidelity_vs_c128": infid_cp}}), flush=True)
 
 
 def workload_adjoint(args):
