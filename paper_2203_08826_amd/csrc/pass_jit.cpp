@@ -800,7 +800,7 @@ std::shared_ptr<JitModule> compile_pass_kernel(const PassProgram &prog, int dtyp
             best = m;
             best_scratch = sc;
         }
-        if (sc == 0) break;
+        if (sc <= 0) break;   // no scratch, or a code object this parser does not read: keep it
     }
     return best;
 }
