@@ -587,6 +587,7 @@ int build_passes_once(qsv_plan *p, int local_bits, bool allow_fold) {
     size_t nfolded = 0;        // pending involutions already folded into passes
     bool relabel_due = false;  // the last fold still has to relabel the gates not yet placed
     std::vector<PGate> run;
+    int run_nd = 0;   // non-diagonal gates in the open pass
     uint64_t S = 0;   // local set (global bits) of the open pass
     auto reset_local = [&]() {
         S = 0;
@@ -635,6 +636,7 @@ int build_passes_once(qsv_plan *p, int local_bits, bool allow_fold) {
         p->ops.push_back(std::move(op));
         p->stats.n_passes++;
         run.clear();
+        run_nd = 0;
         reset_local();
         return QSV_OK;
     };
@@ -671,6 +673,19 @@ int build_passes_once(qsv_plan *p, int local_bits, bool allow_fold) {
     // qubits block later gates accordingly; the scan stops once every qubit
     // is blocked non-diagonally or after a bounded number of gates.
     const uint64_t all = n >= 64 ? ~0ull : (1ull << n) - 1ull;
+    // A gate fits the open pass when its targets fit the chunk and the pass
+    // holds fewer than PASS_MAX_NONDIAG non-diagonal gates: longer passes
+    // (the lookahead can gather 150+ gates) spill registers and take tens
+    // of seconds to compile without saving sweeps.
+    auto fits = [&](const PGate &g) {
+        const uint64_t m = needed(g);
+        return __builtin_popcountll(S | m) <= L && (m == 0 || run_nd < PASS_MAX_NONDIAG);
+    };
+    auto add = [&](const PGate &g) {
+        if (needed(g)) ++run_nd;
+        S |= needed(g);
+        run.push_back(g);
+    };
     auto lookahead = [&](size_t i) {
         uint64_t bnd = 0, bd = 0;
         auto skip = [&](const PGate &h) {
@@ -688,9 +703,8 @@ int build_passes_once(qsv_plan *p, int local_bits, bool allow_fold) {
             uint64_t nd, d;
             acts(h, nd, d);
             const bool commutes = !(nd & (bnd | bd)) && !(d & bnd);
-            if (commutes && h.kind != PGate::OTHER && __builtin_popcountll(S | needed(h)) <= L) {
-                S |= needed(h);
-                run.push_back(h);
+            if (commutes && h.kind != PGate::OTHER && fits(h)) {
+                add(h);
                 done[j] = 1;
             } else {
                 skip(h);
@@ -709,14 +723,13 @@ int build_passes_once(qsv_plan *p, int local_bits, bool allow_fold) {
             p->ops.back().gate_ids = {circuit_index[i]};
             continue;
         }
-        if (__builtin_popcountll(S | needed(pgs[i])) > L) {
+        if (!fits(pgs[i])) {
             lookahead(i);
             int st = close();
             if (st) return st;
             sync_relabel();
         }
-        S |= needed(pgs[i]);
-        run.push_back(pgs[i]);
+        add(pgs[i]);
         done[i] = 1;
     }
     int st = close();

@@ -28,6 +28,7 @@ constexpr int PASS_MAX_RB = 5;
 constexpr int PASS_MAX_L = PASS_MAX_RB + PASS_MAX_THREAD_BITS;
 constexpr int PASS_MAX_SLOTS = 64;       // per op: one per lane of a wave
 constexpr size_t PASS_LOOKAHEAD = 4096;   // gates a pass planner scans past one that does not fit
+constexpr int PASS_MAX_NONDIAG = 64;      // non-diagonal gates per pass
 constexpr int PASS_SLOT_TERMS = 32;      // longer slots are split
 
 enum PassOpKind : int32_t { POP_EXCHANGE = 1, POP_G1 = 2, POP_G1R = 3, POP_G2 = 4, POP_PHASE = 5 };
