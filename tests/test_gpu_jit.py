@@ -199,3 +199,23 @@ def test_final_permutation_as_two_involutions(gpu, jit, dt):
     got, stats = _run(psi0, circ, dt, mode=qsv.PLAN_PASSES, local_bits=lb, jit=jit)
     assert stats["n_gate_ops"] == 0, stats
     assert np.array_equal(got, S.run_circuit(psi0, circ))
+
+
+@pytest.mark.parametrize("dt", [qsv.QSV_C64, qsv.QSV_C128])
+def test_jit_deep_supremacy_with_lookahead(gpu, dt):
+    """A 20-qubit depth-16 supremacy-like circuit: later gates that commute
+    with the skipped ones join open passes, at most 64 non-diagonal gates
+    per pass; the result matches the oracle."""
+    n = 20
+    circ = W.supremacy(n, 16, seed=11)
+    psi0 = W.random_state(n, 6)
+    want = S.run_circuit(psi0, circ)
+    got, stats = _run(psi0, circ, dt, mode=qsv.PLAN_PASSES, jit=1)
+    assert np.max(np.abs(got - want)) <= 3 * TOL[dt], stats
+    p = qsv.qsv_plan_create(n, dt, circ, mode=qsv.PLAN_PASSES, jit=1)
+    order = []
+    for k in range(p.stats()["n_launches"]):
+        ids = qsv.qsv_plan_op_gates(p, k)
+        assert sum(circ[i]["name"] != "CZ" for i in ids) <= 64
+        order += ids
+    assert sorted(order) == list(range(len(circ))) and order != sorted(order)
