@@ -433,6 +433,8 @@ std::string Gen::source() {
     ln("__device__ __forceinline__ C cml(C a, R re, R im) { C r; r.x = a.x * re - a.y * im; r.y = a.x * im + a.y * re; "
        "return r; }");
     ln("__device__ __forceinline__ C rot1(C a) { C r; r.x = -a.y; r.y = a.x; return r; }");    // a * i
+    ln("__device__ __forceinline__ C rot2(C a) { C r; r.x = -a.x; r.y = -a.y; return r; }");   // a * -1
+    ln("__device__ __forceinline__ C rot3(C a) { C r; r.x = a.y; r.y = -a.x; return r; }");    // a * -i
     // global accesses as a uniform 64-bit base (scalar registers) plus a
     // 32-bit per-thread byte offset: one address form of the memory
     // instruction, no 64-bit vector address arithmetic per access
@@ -442,8 +444,6 @@ std::string Gen::source() {
     ln("           (unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)x); }");
     ln("__device__ __forceinline__ C ldg(unsigned long long ub, unsigned off) { return *(const GLB C *)((const GLB char *)ub + off); }");
     ln("__device__ __forceinline__ void stg(unsigned long long ub, unsigned off, C v) { *(GLB C *)((GLB char *)ub + off) = v; }");
-    ln("__device__ __forceinline__ C rot2(C a) { C r; r.x = -a.x; r.y = -a.y; return r; }");   // a * -1
-    ln("__device__ __forceinline__ C rot3(C a) { C r; r.x = a.y; r.y = -a.x; return r; }");    // a * -i
     if (f32) {
         ln("__device__ __forceinline__ C expi(unsigned long long ph) {");
         ln("    const float x = (float)(int)(unsigned)(ph >> 32) * 2.3283064365386963e-10f;");
