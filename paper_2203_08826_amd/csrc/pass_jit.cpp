@@ -22,35 +22,43 @@
 #include <elf.h>
 #include <map>
 #include <mutex>
-#include <thread>
 #include <unordered_map>
 
 #include "plan_internal.h"
 
 namespace qsv {
 
-struct JitModule {
+// A code object holding the kernels of one or more passes (compiled
+// together), loaded on a device at the first launch of any of them.
+struct JitCode {
     std::vector<char> code;                 // code object for gfx950
-    std::string source;                     // the kernel source it was compiled from
-    bool prefetch = false;                  // persistent workgroups with a prefetched next chunk
     std::mutex mu;
-    struct Loaded {
-        hipModule_t mod = nullptr;
-        hipFunction_t fn = nullptr;
-        int grid_per_cu = 0;
-    };
-    std::map<int, Loaded> dev;              // per device, loaded on first launch
-    ~JitModule() {
-        for (auto &kv : dev)
-            if (kv.second.mod) {
+    std::map<int, hipModule_t> mod;         // per device
+    ~JitCode() {
+        for (auto &kv : mod)
+            if (kv.second) {
                 int cur = 0;
                 (void)hipGetDevice(&cur);
                 (void)hipSetDevice(kv.first);
                 (void)hipDeviceSynchronize();   // no launch of this module may still run
-                (void)hipModuleUnload(kv.second.mod);
+                (void)hipModuleUnload(kv.second);
                 (void)hipSetDevice(cur);
             }
     }
+};
+
+// One compiled pass: its kernel in a (shared) code object.
+struct JitModule {
+    std::shared_ptr<JitCode> code;
+    std::string kernel;                     // the kernel's name in the code object
+    std::string source;                     // the pass's kernel source (as one program of its own)
+    bool prefetch = false;                  // persistent workgroups with a prefetched next chunk
+    std::mutex mu;
+    struct Loaded {
+        hipFunction_t fn = nullptr;
+        int grid_per_cu = 0;
+    };
+    std::map<int, Loaded> dev;              // per device, found on first launch
 };
 
 // Persistent workgroups that load the next chunk while computing the current
@@ -770,39 +778,98 @@ long kernel_scratch_bytes(const std::vector<char> &co, const std::string &kernel
 
 }  // namespace
 
-// Compiles a pass, first as `first` (the default variant's source).  A
-// kernel whose registers spill to scratch is compiled again without shared
-// phase products, then without the prefetched chunk, then without both
-// (each frees registers).  A prefetching variant is kept if it spills at
-// most a few values (measured: cheaper than giving up the prefetch); else
-// the first variant without scratch, else the one with the least.
-std::shared_ptr<JitModule> compile_pass_kernel(const PassProgram &prog, int dtype, const std::string &first,
-                                               std::string &err) {
+// Compiles several generated sources as one program: hiprtc serialises
+// compilations within a process and each costs a fixed ~0.25 s on top of
+// code generation, so the kernels of a plan share one compilation.  Kernel
+// u is renamed qsv_pass_jit_u; sources whose shared preamble (the helpers
+// before the kernel) differs go to separate programs.
+int compile_batch(const std::vector<std::string> &srcs, std::vector<std::shared_ptr<JitCode>> &codes,
+                  std::vector<std::string> &names, std::string &err) {
+    const std::string marker = "extern \"C\" __global__";
+    const std::string call = std::string(JIT_KERNEL_NAME) + "(";
+    codes.assign(srcs.size(), nullptr);
+    names.assign(srcs.size(), std::string());
+    std::map<std::string, std::vector<size_t>> groups;   // preamble -> sources
+    for (size_t u = 0; u < srcs.size(); ++u) {
+        const size_t k = srcs[u].find(marker);
+        groups[k == std::string::npos ? std::string() : srcs[u].substr(0, k)].push_back(u);
+    }
+    for (auto &g : groups) {
+        std::string prog = g.first;
+        for (size_t u : g.second) {
+            const std::string &src = srcs[u];
+            const size_t k = src.find(marker);
+            const size_t c = src.find(call, k == std::string::npos ? 0 : k);
+            if (k == std::string::npos || c == std::string::npos) {
+                err = "generated pass source without its kernel";
+                return -1;
+            }
+            names[u] = fmt("%s_%zu", JIT_KERNEL_NAME, u);
+            prog += src.substr(k, c - k) + names[u] + "(" + src.substr(c + call.size()) + "\n";
+        }
+        auto code = std::make_shared<JitCode>();
+        if (compile_source(prog, code->code, err)) return -1;
+        for (size_t u : g.second) codes[u] = code;
+    }
+    return 0;
+}
+
+// Compiles the passes `progs` (first as their default variant `first`), all
+// kernels of a round in one program.  A kernel whose registers spill to
+// scratch is compiled again without shared phase products, then without the
+// prefetched chunk, then without both (each frees registers).  A
+// prefetching variant is kept if it spills at most a few values (measured:
+// cheaper than giving up the prefetch); else the first variant without
+// scratch, else the one with the least.
+int compile_pass_kernels(const std::vector<const PassProgram *> &progs, int dtype, const std::vector<std::string> &first,
+                         std::vector<std::shared_ptr<JitModule>> &out, std::string &err) {
     const JitVariant vs[4] = {{true, true}, {false, true}, {true, false}, {false, false}};
     constexpr long SMALL_SPILL = 16;   // bytes per lane
-    std::shared_ptr<JitModule> best;
-    long best_scratch = -1;
-    std::vector<std::string> tried;
+    const size_t N = progs.size();
+    out.assign(N, nullptr);
+    std::vector<long> best_sc(N, -1);
+    std::vector<std::vector<std::string>> tried(N);
+    std::vector<char> done(N, 0);
     for (int vi = 0; vi < 4; ++vi) {
-        const JitVariant &v = vs[vi];
-        if (vi == 2 && best && best->prefetch && best_scratch >= 0 && best_scratch <= SMALL_SPILL) break;
-        std::string src = tried.empty() ? first : pass_jit_source(prog, dtype, v);
-        bool seen = false;
-        for (auto &t : tried) seen = seen || t == src;
-        if (seen) continue;
-        tried.push_back(src);
-        auto m = std::make_shared<JitModule>();
-        if (compile_source(src, m->code, err)) return best;
-        const long sc = kernel_scratch_bytes(m->code, JIT_KERNEL_NAME);
-        m->source.swap(src);
-        m->prefetch = v.prefetch && pass_jit_prefetch(prog, dtype);
-        if (!best || (sc >= 0 && (best_scratch < 0 || sc < best_scratch))) {
-            best = m;
-            best_scratch = sc;
+        std::vector<size_t> items;
+        std::vector<std::string> srcs;
+        for (size_t i = 0; i < N; ++i) {
+            if (done[i]) continue;
+            if (vi == 2 && out[i] && out[i]->prefetch && best_sc[i] >= 0 && best_sc[i] <= SMALL_SPILL) {
+                done[i] = 1;
+                continue;
+            }
+            std::string src = vi == 0 ? first[i] : pass_jit_source(*progs[i], dtype, vs[vi]);
+            bool seen = false;
+            for (auto &t : tried[i]) seen = seen || t == src;
+            if (seen) continue;
+            tried[i].push_back(src);
+            items.push_back(i);
+            srcs.push_back(std::move(src));
         }
-        if (sc <= 0) break;   // no scratch, or a code object this parser does not read: keep it
+        if (items.empty()) continue;
+        std::vector<std::shared_ptr<JitCode>> codes;
+        std::vector<std::string> names;
+        if (compile_batch(srcs, codes, names, err)) {
+            if (vi == 0) return -1;
+            break;   // keep the variants compiled so far
+        }
+        for (size_t r = 0; r < items.size(); ++r) {
+            const size_t i = items[r];
+            const long sc = kernel_scratch_bytes(codes[r]->code, names[r]);
+            auto m = std::make_shared<JitModule>();
+            m->code = codes[r];
+            m->kernel = names[r];
+            m->source = srcs[r];
+            m->prefetch = vs[vi].prefetch && pass_jit_prefetch(*progs[i], dtype);
+            if (!out[i] || (sc >= 0 && (best_sc[i] < 0 || sc < best_sc[i]))) {
+                out[i] = m;
+                best_sc[i] = sc;
+            }
+            if (sc <= 0) done[i] = 1;   // no scratch, or a code object this parser does not read: keep it
+        }
     }
-    return best;
+    return 0;
 }
 
 int jit_compile_plan(qsv_plan *p) {
@@ -822,32 +889,21 @@ int jit_compile_plan(qsv_plan *p) {
             else todo.push_back(i);
         }
     }
-    // distinct sources compile side by side
+    // distinct sources, compiled together
     std::map<std::string, size_t> first;
     std::vector<size_t> uniq;
     for (size_t i : todo)
         if (first.emplace(srcs[i], i).second) uniq.push_back(i);
-    std::vector<std::string> errs(uniq.size());
-    std::vector<std::shared_ptr<JitModule>> built(uniq.size());
-    size_t nth = std::max<size_t>(1, std::min<size_t>(uniq.size(), std::min(16u, std::max(1u, std::thread::hardware_concurrency()))));
-    std::vector<std::thread> th;
-    std::mutex next_mu;
-    size_t next = 0;
-    for (size_t w = 0; w < nth; ++w)
-        th.emplace_back([&] {
-            for (;;) {
-                size_t u;
-                {
-                    std::lock_guard<std::mutex> lk(next_mu);
-                    if (next >= uniq.size()) return;
-                    u = next++;
-                }
-                built[u] = compile_pass_kernel(*progs[uniq[u]], p->dtype, srcs[uniq[u]], errs[u]);
-            }
-        });
-    for (auto &x : th) x.join();
-    for (size_t u = 0; u < uniq.size(); ++u)
-        if (!built[u]) return fail(QSV_ERR_UNSUPPORTED, "pass kernel compilation failed: " + errs[u]);
+    std::vector<const PassProgram *> uprogs;
+    std::vector<std::string> usrcs;
+    for (size_t i : uniq) {
+        uprogs.push_back(progs[i]);
+        usrcs.push_back(srcs[i]);
+    }
+    std::vector<std::shared_ptr<JitModule>> built;
+    std::string err;
+    if (!uniq.empty() && compile_pass_kernels(uprogs, p->dtype, usrcs, built, err))
+        return fail(QSV_ERR_UNSUPPORTED, "pass kernel compilation failed: " + err);
     {
         std::lock_guard<std::mutex> lk(cache_mu);
         if (cache.size() + uniq.size() > CACHE_MAX) cache.clear();   // plans keep their own modules
@@ -871,13 +927,21 @@ int launch_pass_jit(void *state, int n, int dtype, const PassProgram &prog, hipS
     {
         std::lock_guard<std::mutex> lk(jm.mu);
         JitModule::Loaded &ld = jm.dev[dev];
-        if (!ld.mod) {
-            if ((e = hipModuleLoadData(&ld.mod, jm.code.data())) != hipSuccess) {
-                ld.mod = nullptr;
-                return hip_fail(e, "loading a compiled pass kernel");
+        if (!ld.fn) {
+            hipModule_t mod = nullptr;
+            {
+                std::lock_guard<std::mutex> lc(jm.code->mu);
+                hipModule_t &m = jm.code->mod[dev];
+                if (!m && (e = hipModuleLoadData(&m, jm.code->code.data())) != hipSuccess) {
+                    m = nullptr;
+                    return hip_fail(e, "loading a compiled pass kernel");
+                }
+                mod = m;
             }
-            if ((e = hipModuleGetFunction(&ld.fn, ld.mod, JIT_KERNEL_NAME)) != hipSuccess)
+            if ((e = hipModuleGetFunction(&ld.fn, mod, jm.kernel.c_str())) != hipSuccess) {
+                ld.fn = nullptr;
                 return hip_fail(e, "finding the compiled pass kernel");
+            }
             int b = 0;
             if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&b, ld.fn, 1 << prog.TB, 0) != hipSuccess || b < 1)
                 b = 1;
