@@ -26,7 +26,7 @@ def test_gradient_matches_oracle(gpu, dt, tol, n, layers):
     e.backward()
     got = theta.grad.cpu().numpy()
     ps = OA.grad_param_shift(circ, n)
-    assert abs(float(e) - OA.expval(circ, n)) <= (1e-12 if dt == qsv.QSV_C128 else 1e-4)
+    assert abs(float(e.detach()) - OA.expval(circ, n)) <= (1e-12 if dt == qsv.QSV_C128 else 1e-4)
     assert np.max(np.abs(got - ps)) <= tol
     if n <= 6:
         fd = OA.grad_fd(circ, n, step=1e-5)
