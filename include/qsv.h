@@ -167,7 +167,9 @@ typedef struct qsv_plan_options {
                         * qsv_plan_create) into a kernel specialised for its
                         * gates -- constants, bit assignments and op sequence
                         * fixed at compile time; results equal the interpreted
-                        * pass kernel's up to rounding order.  0: interpreted. */
+                        * pass kernel's up to rounding (matrix and phase entries
+                        * within 2^-50 of 0 or +-1 are taken as exact).
+                        * 0: interpreted. */
 } qsv_plan_options;
 
 typedef struct qsv_plan qsv_plan;
@@ -188,8 +190,10 @@ typedef struct qsv_plan_stats {
 
 /* Build a plan on the host (no HIP call unless mode = LEARNED with a model,
  * which runs the MLP inference kernel on the current device).  With
- * opts->jit the passes are compiled here (host compiler only; each kernel is
- * loaded on a device at its first execution there); a compilation failure
+ * opts->jit the passes are compiled here (host compiler only; the plan's
+ * kernels in one program, a kernel that spills registers compiled again in
+ * a leaner variant; each code object is loaded on a device at the first
+ * execution of one of its kernels there); a compilation failure
  * returns QSV_ERR_UNSUPPORTED with the compiler log in qsv_last_error.  The
  * gates are copied; the caller may free them afterwards. */
 int qsv_plan_create(int n, int dtype, const qsv_gate *gates, int ngates,
@@ -209,9 +213,10 @@ int qsv_plan_op_info(const qsv_plan *plan, int index, int *kind, double *bytes, 
  * plan_internal.h: header, partitions, ops, real pool, phase terms, slots; the pool
  * is stored as doubles) into buf (cap bytes); *size receives the length. */
 int qsv_plan_op_program(const qsv_plan *plan, int index, void *buf, size_t cap, size_t *size);
-/* Host-only: the HIP source of the kernel that op `index` (an LDS pass)
- * compiles to when the plan is built with opts->jit, NUL-terminated, into
- * buf (cap bytes); *size receives the length including the NUL. */
+/* Host-only: the HIP source of the kernel of op `index` (an LDS pass): the
+ * variant compiled when the plan was built with opts->jit, else the one it
+ * would compile to first; NUL-terminated, into buf (cap bytes); *size
+ * receives the length including the NUL. */
 int qsv_plan_op_source(const qsv_plan *plan, int index, char *buf, size_t cap, size_t *size);
 /* Host-only: the circuit indices (positions in the gate array given to
  * qsv_plan_create) of the gates op `index` applies, in the order it applies
