@@ -122,9 +122,8 @@ __device__ __forceinline__ void unit_bases(uint64_t w0, uint64_t wstride, uint64
     }
 }
 
-template <typename C, int M, int VG>
+template <typename C, int M, int VG, int U>
 __global__ void __launch_bounds__(256) k_dense(C *__restrict__ psi, GroupArgs ga, DenseArgs<C, M> da) {
-    constexpr int U = Unroll<C, M>::U;
     const uint64_t nunits = ga.ngroups / VG;
     const uint64_t span = (uint64_t)U * blockDim.x;
     for (uint64_t w0 = (uint64_t)blockIdx.x * span + threadIdx.x; w0 < nunits; w0 += (uint64_t)gridDim.x * span) {
@@ -190,9 +189,8 @@ __global__ void __launch_bounds__(256) k_diag(C *__restrict__ psi, GroupArgs ga,
     }
 }
 
-template <typename C, int M, int VG>
+template <typename C, int M, int VG, int U>
 __global__ void __launch_bounds__(256) k_perm(C *__restrict__ psi, GroupArgs ga, PermArgs<C, M> pa) {
-    constexpr int U = Unroll<C, M>::U;
     const uint64_t nunits = ga.ngroups / VG;
     const uint64_t span = (uint64_t)U * blockDim.x;
     for (uint64_t w0 = (uint64_t)blockIdx.x * span + threadIdx.x; w0 < nunits; w0 += (uint64_t)gridDim.x * span) {
@@ -327,6 +325,17 @@ template <typename C> static C to_c(const double *z) {
     return r;
 }
 
+// Paired complex64 groups with 16-byte members stream best with one unit
+// per thread unless the members lie far apart (2^24 amplitudes or more),
+// where four units keep more loads in flight (30 qubits, one-qubit gate on
+// qubit 10: 5.28 -> 5.65 TB/s with one unit; on qubit 29: 5.44 with four,
+// 5.24 with one).
+static bool members_far(const GateAnalysis &a, int M) {
+    uint64_t top = 0;
+    for (int j = 0; j < M; ++j) top = std::max<uint64_t>(top, a.offs[j]);
+    return top >= (1ull << 24);
+}
+
 template <typename C, int M>
 static void launch_dense_m(C *psi, const GateAnalysis &a, const GroupArgs &ga, const C *dmat, hipStream_t s) {
     DenseArgs<C, M> da;
@@ -335,9 +344,11 @@ static void launch_dense_m(C *psi, const GateAnalysis &a, const GroupArgs &ga, c
     if (M <= 8)
         for (int j = 0; j < M * M; ++j) da.mat[j] = to_c<C>(&a.mat[2 * j]);
     da.dmat = dmat;
-    constexpr int PB = 256 * Unroll<C, M>::U;
-    if (vg2(ga)) hipLaunchKernelGGL((k_dense<C, M, 2>), dim3(grid_for(ga.ngroups / 2, PB)), dim3(256), 0, s, psi, ga, da);
-    else hipLaunchKernelGGL((k_dense<C, M, 1>), dim3(grid_for(ga.ngroups, PB)), dim3(256), 0, s, psi, ga, da);
+    constexpr int UU = Unroll<C, M>::U;
+    if (!vg2(ga)) hipLaunchKernelGGL((k_dense<C, M, 1, UU>), dim3(grid_for(ga.ngroups, 256 * UU)), dim3(256), 0, s, psi, ga, da);
+    else if (UU > 1 && !members_far(a, M))
+        hipLaunchKernelGGL((k_dense<C, M, 2, 1>), dim3(grid_for(ga.ngroups / 2, 256)), dim3(256), 0, s, psi, ga, da);
+    else hipLaunchKernelGGL((k_dense<C, M, 2, UU>), dim3(grid_for(ga.ngroups / 2, 256 * UU)), dim3(256), 0, s, psi, ga, da);
 }
 
 template <typename C, int M>
@@ -366,9 +377,11 @@ static void launch_perm_m(C *psi, const GateAnalysis &a, const GroupArgs &ga, hi
         pa.fac[j] = to_c<C>(&a.mat[2 * j]);
         if (a.perm_one[j]) pa.one |= 1ull << j;
     }
-    constexpr int PB = 256 * Unroll<C, M>::U;
-    if (vg2(ga)) hipLaunchKernelGGL((k_perm<C, M, 2>), dim3(grid_for(ga.ngroups / 2, PB)), dim3(256), 0, s, psi, ga, pa);
-    else hipLaunchKernelGGL((k_perm<C, M, 1>), dim3(grid_for(ga.ngroups, PB)), dim3(256), 0, s, psi, ga, pa);
+    constexpr int UU = Unroll<C, M>::U;
+    if (!vg2(ga)) hipLaunchKernelGGL((k_perm<C, M, 1, UU>), dim3(grid_for(ga.ngroups, 256 * UU)), dim3(256), 0, s, psi, ga, pa);
+    else if (UU > 1 && !members_far(a, M))
+        hipLaunchKernelGGL((k_perm<C, M, 2, 1>), dim3(grid_for(ga.ngroups / 2, 256)), dim3(256), 0, s, psi, ga, pa);
+    else hipLaunchKernelGGL((k_perm<C, M, 2, UU>), dim3(grid_for(ga.ngroups / 2, 256 * UU)), dim3(256), 0, s, psi, ga, pa);
 }
 
 // Low-qubit path for a one-target dense gate whose target is below the
