@@ -222,3 +222,18 @@ def test_chunk_pair_enumeration_covers_each_pair_once(n, circ_kind):
     chunks = {b for k in seen for b in k}
     L = 12
     assert len(chunks) == 1 << (n - L)
+
+
+def test_op_gates_of_per_gate_and_greedy_plans():
+    """qsv_plan_op_gates on the other planners: one gate per op in circuit
+    order for per-gate plans; the greedy blocks' members for fused plans."""
+    n = 10
+    circ = W.random_circuit(n, 80, seed=5, kmax=2, max_controls=1)
+    p = qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_PER_GATE)
+    assert [qsv.qsv_plan_op_gates(p, k) for k in range(p.stats()["n_launches"])] == [[i] for i in range(len(circ))]
+    g = qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_GREEDY, kmax=3)
+    ops = [qsv.qsv_plan_op_gates(g, k) for k in range(g.stats()["n_launches"])]
+    assert sorted(i for o in ops for i in o) == list(range(len(circ)))
+    blocks = qsv.qsv_plan_blocks(g)
+    for b, members in enumerate(ops):
+        assert all(blocks[i] == b for i in members)
