@@ -352,6 +352,7 @@ def main():
     # ---------------------------------------------------------- dominant kernel roofline (HIP events)
     nops = pstats["n_launches"]
     per_kind = {}
+    per_launch_ms = []
     reps = 3
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -363,6 +364,7 @@ def main():
         ev1.record(stream)
         ev1.synchronize()
         dur = ev0.elapsed_time(ev1) / 1e3 / reps
+        per_launch_ms.append(round(dur * 1e3, 3))
         k = per_kind.setdefault(info["kind"], {"time": 0.0, "count": 0, "bytes": 0.0, "flops": 0.0})
         k["time"] += dur
         k["count"] += 1
@@ -378,7 +380,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kind_names[dom]),
                 "kernel": kind_names[dom], "launches": d["count"], "avg_launch_ms": round(avg_dur * 1e3, 4),
-                "bytes_per_launch": bytes_per_launch}
+                "bytes_per_launch": bytes_per_launch, "per_launch_ms": per_launch_ms}
 
     # ---------------------------------------------------------- comparison plans
     compare = {}
