@@ -231,6 +231,23 @@ def workload_learned(args):
         flush=True)
 
 
+def host_description():
+    """CPU model, logical CPUs and memory of the host the oracle ran on."""
+    model, mem_kib = "unknown CPU", 0
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal:"):
+                mem_kib = int(line.split()[1])
+                break
+    except OSError:
+        pass
+    return "%s, %d logical CPUs, %.0f GiB RAM" % (model, os.cpu_count() or 0, mem_kib / 2 ** 20)
+
+
 def measured_traffic(kind):
     """HBM bytes per launch of the dominant kernel from the committed
     FETCH_SIZE / WRITE_SIZE summary (scaled by the copy-kernel calibration),
@@ -426,7 +443,8 @@ def main():
         per_gate = dt_cpu / k
         cpu = {"value": round(per_gate * len(circ), 2), "unit": "s", "cores": S.num_threads(), "kind": "oracle",
                "sample": "first %d gates of the %d-qubit QFT (complex128, out of place), %.2f s measured; "
-                         "value = mean seconds per gate x %d gates" % (k, n, dt_cpu, len(circ))}
+                         "value = mean seconds per gate x %d gates" % (k, n, dt_cpu, len(circ)),
+               "host": host_description()}
         del a, b
 
     gbps = bytes_plan / step_s / 1e9
