@@ -19,6 +19,8 @@ What is here, each written from the paper's statement of the problem:
   benchmark circuits.
 * ``adjoint``: adjoint-method gradients, parameter shift, finite differences.
 * ``mlp``: float64 numpy forward/backward/Adam of the fusion cost model.
+* ``measure``: collapse and re-normalisation onto a measurement outcome,
+  inverse-CDF shot sampling and Metropolis shot frequencies (Sec. 2).
 
 Every function states the passage it follows.  Functions with nothing but the
 code itself to check them against say "parity unpinned".
