@@ -12,7 +12,8 @@ al. 1953).  The paper gives no formulas; the readings used here:
   amplitude becomes 0;
 * inverse-CDF sampling: with c_m = p_0 + ... + p_m (summed in index order)
   and T = c_{R-1}, a uniform u in [0, 1) gives the smallest m with
-  u T < c_m;
+  u T < c_m; when the product u T rounds up to T, the last outcome of
+  non-zero probability;
 * Metropolis frequencies: independent chains; chain c starts at outcome
   x = start_c and at each step s takes the proposal y = y_{s,c} when
   u_{s,c} p(x) < p(y) (acceptance probability min(1, p(y)/p(x)), a proposal
@@ -63,11 +64,15 @@ def cumulative(probs):
 
 def sample_inverse_cdf(probs, uniforms):
     """Smallest m with u T < c_m for every uniform u (T = c_{R-1}); a binary
-    search of the sorted c (numpy's searchsorted), clamped to R - 1 for a
-    product u T that rounds up to T."""
-    c = cumulative(probs)
+    search of the sorted c (numpy's searchsorted); the last outcome of
+    non-zero probability when u T rounds up to T."""
+    p = np.asarray(probs, dtype=np.float64)
+    c = cumulative(p)
     x = np.asarray(uniforms, dtype=np.float64) * c[-1]
-    return np.minimum(np.searchsorted(c, x, side="right"), c.size - 1).astype(np.int64)
+    m = np.searchsorted(c, x, side="right")
+    nz = np.nonzero(p)[0]
+    last = int(nz[-1]) if nz.size else 0
+    return np.where(m >= c.size, last, m).astype(np.int64)
 
 
 def metropolis_counts(probs, starts, proposals, uniforms):
