@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--model", default=os.path.join(ROOT, "paper_2203_08826_amd", "cost_model.npz"))
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only time a plain device copy of 2^n complex64 (HBM ceiling and counter calibration)")
-    ap.add_argument("--workload", default="qft", choices=["qft", "supremacy", "variational", "adjoint", "learned"],
+    ap.add_argument("--workload", default="qft", choices=["qft", "supremacy", "variational", "adjoint", "learned", "single_gate"],
                     help="qft: the headline line; the others print their own configuration's line")
     ap.add_argument("--depth", type=int, default=20)
     ap.add_argument("--layers", type=int, default=40)
@@ -231,6 +231,53 @@ def workload_learned(args):
         flush=True)
 
 
+def workload_single_gate(args):
+    """Per-gate kernels on their own: dense one-qubit gates on a low, middle
+    and high qubit, X, Z, a controlled phase, SWAP and fSim, each timed with
+    HIP events on the launch stream over --steps launches, GB/s of touched
+    bytes (read + write of the amplitudes the gate changes)."""
+    import numpy as np
+    import torch
+    import paper_2203_08826_amd as qsv
+    n = args.n
+    H = np.array([[1, 1], [1, -1]]) / np.sqrt(2)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for dname, tdt, s in (("c64", torch.complex64, 8), ("c128", torch.complex128, 16)):
+        st = torch.zeros(1 << n, dtype=tdt, device="cuda")
+        st[0] = 1.0
+        full = 2.0 * (1 << n) * s
+        cases = (("H_q0", lambda: qsv.qsv_apply_matrix(st, H, [0]), full),
+                 ("H_q3", lambda: qsv.qsv_apply_matrix(st, H, [3]), full),
+                 ("H_q12", lambda: qsv.qsv_apply_matrix(st, H, [12]), full),
+                 ("H_q%d" % (n - 8), lambda: qsv.qsv_apply_matrix(st, H, [n - 8]), full),
+                 ("H_q%d" % (n - 1), lambda: qsv.qsv_apply_matrix(st, H, [n - 1]), full),
+                 ("X_q%d" % (n - 1), lambda: qsv.qsv_apply_x(st, n - 1), full),
+                 ("Z_q5", lambda: qsv.qsv_apply_z(st, 5), full / 2),
+                 ("CU1_c3_t20", lambda: qsv.qsv_apply_phase(st, 20, 0.3, [3]), full / 4),
+                 ("SWAP_3_20", lambda: qsv.qsv_apply_swap(st, 3, 20), full / 2),
+                 ("fSim_10_20", lambda: qsv.qsv_apply_fsim(st, 10, 20, 0.4, 0.7), full * 0.75))
+        for name, fn, nbytes in cases:
+            fn()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                fn()
+            e1.record(stream)
+            e1.synchronize()
+            sec = e0.elapsed_time(e1) / 1e3 / args.steps
+            res["%s_%s" % (name, dname)] = {"ms": round(sec * 1e3, 3), "GB/s": round(nbytes / sec / 1e9, 1),
+                                            "frac": round(nbytes / sec / 1e9 / HBM_PEAK_GBS, 4)}
+            print("single_gate %s %s %.3f ms %.1f GB/s" % (dname, name, sec * 1e3, nbytes / sec / 1e9), flush=True)
+        del st
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "single-gate HBM GB/s (touched bytes)", "config": {
+        "workload": "single gates at n=%d, complex64 and complex128, %d launches each" % (n, args.steps)},
+        "peak_GB/s": HBM_PEAK_GBS, "results": res}), flush=True)
+
+
 def host_description():
     """CPU model, logical CPUs and memory of the host the oracle ran on."""
     model, mem_kib = "unknown CPU", 0
@@ -308,7 +355,7 @@ def main():
         return
     if args.workload != "qft":
         {"supremacy": workload_supremacy, "variational": workload_variational, "adjoint": workload_adjoint,
-         "learned": workload_learned}[args.workload](args)
+         "learned": workload_learned, "single_gate": workload_single_gate}[args.workload](args)
         return
 
     dev = torch.device("cuda:0")

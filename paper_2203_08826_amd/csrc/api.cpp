@@ -262,6 +262,7 @@ GateAnalysis analyse_gate(int n, const double *G, const int *targets, int k, con
 namespace {
 constexpr int kSlots = 256;
 constexpr size_t kSlotBytes = 256 << 10;
+constexpr int kMaxStagingSlots = 8;   // the largest request: 2 MiB in consecutive slots
 
 struct DeviceStaging {
     bool ready = false;
@@ -278,7 +279,8 @@ DeviceStaging g_staging[64];
 size_t staging_slot_bytes() { return kSlotBytes; }
 
 int staging_acquire(size_t bytes, StagingSlot *slot) {
-    if (bytes > kSlotBytes) return fail(QSV_ERR_ARG, "staging request above the slot size");
+    if (bytes > kMaxStagingSlots * kSlotBytes) return fail(QSV_ERR_ARG, "staging request above the largest span");
+    const int span = bytes <= kSlotBytes ? 1 : (int)((bytes + kSlotBytes - 1) / kSlotBytes);
     int dev = 0;
     QSV_HIP_CHECK(hipGetDevice(&dev));
     if (dev < 0 || dev >= 64) return fail(QSV_ERR_ARG, "device index above 63");
@@ -293,16 +295,21 @@ int staging_acquire(size_t bytes, StagingSlot *slot) {
         }
         st.ready = true;
     }
+    // a request of several slots takes consecutive ones (wrapping to slot 0
+    // when the ring's end would split it)
+    if (st.next + span > kSlots) st.next = 0;
     const int i = st.next;
-    st.next = (st.next + 1) % kSlots;
-    if (st.armed[i]) {
-        QSV_HIP_CHECK(hipEventSynchronize(st.ev[i]));
-        st.armed[i] = false;
-    }
+    st.next = (st.next + span) % kSlots;
+    for (int j = i; j < i + span; ++j)
+        if (st.armed[j]) {
+            QSV_HIP_CHECK(hipEventSynchronize(st.ev[j]));
+            st.armed[j] = false;
+        }
     slot->host = st.host + (size_t)i * kSlotBytes;
     slot->dev = st.dev + (size_t)i * kSlotBytes;
-    slot->bytes = kSlotBytes;
+    slot->bytes = (size_t)span * kSlotBytes;
     slot->index = i + dev * kSlots;
+    slot->span = span;
     return QSV_OK;
 }
 
@@ -314,8 +321,10 @@ int staging_upload(const StagingSlot &slot, size_t bytes, hipStream_t s) {
 int staging_release(const StagingSlot &slot, hipStream_t s) {
     const int dev = slot.index / kSlots, i = slot.index % kSlots;
     std::lock_guard<std::mutex> lk(g_staging_mu);
-    QSV_HIP_CHECK(hipEventRecord(g_staging[dev].ev[i], s));
-    g_staging[dev].armed[i] = true;
+    for (int j = i; j < i + slot.span; ++j) {
+        QSV_HIP_CHECK(hipEventRecord(g_staging[dev].ev[j], s));
+        g_staging[dev].armed[j] = true;
+    }
     return QSV_OK;
 }
 

@@ -164,6 +164,11 @@ int build_learned(qsv_plan *p) {
     std::vector<const qsv_plan *> cands;
     for (auto &c : owned)
         if (c) cands.push_back(c.get());
+    if (cands.empty()) {   // no candidate could be built: the documented fallback
+        int st2 = build_greedy(p, kfb, p->opts.use_mfma != 0);
+        p->stats.mode_used = QSV_PLAN_GREEDY;
+        return st2;
+    }
     std::vector<double> t;
     int st = predict(*m, cands, t);
     if (st) return st;

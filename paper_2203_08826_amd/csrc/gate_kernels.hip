@@ -296,10 +296,13 @@ __global__ void __launch_bounds__(256) k_low1(C *__restrict__ psi, Low1Args<C> a
 // ------------------------------------------------------------------ launch
 
 // Workgroups for `items` units at `per_block` units each: one pass over the
-// state (the loops in the kernels only run again beyond the grid limit).
+// state (the loops in the kernels only run again beyond the grid limit).  A
+// launch holds fewer than 2^32 threads in all (HIP's limit on the total work
+// size), so 256-thread workgroups number at most 2^24 - 1: a 33-qubit
+// complex128 gate with 2^32 groups takes two rounds of its loop.
 static int grid_for(uint64_t items, uint64_t per_block) {
     uint64_t blocks = (items + per_block - 1) / per_block;
-    const uint64_t cap = 0x7fffffffull;
+    const uint64_t cap = 0xffffffffull / 256;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
     return (int)blocks;

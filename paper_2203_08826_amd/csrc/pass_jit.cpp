@@ -475,6 +475,9 @@ std::string Gen::source() {
     ln("    __builtin_amdgcn_s_barrier();");
     ln("    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, \"workgroup\", \"local\"); }");
     ln("__device__ __forceinline__ unsigned swz(unsigned l) { return l ^ (((l >> 4) ^ (l >> 8) ^ (l >> 12)) & 15u); }");
+    // an amplitude as an operand of an empty volatile asm: its load has
+    // completed (the compiler waits for it) before anything after this point
+    ln("__device__ __forceinline__ void hold(C v) { asm volatile(\"\" :: \"v\"(v.x), \"v\"(v.y)); }");
     ln("");
     ln(fmt("extern \"C\" __global__ void __launch_bounds__(%d) %s(C *__restrict__ psi, const unsigned char "
            "*__restrict__ prog, unsigned long long nchunks) {",
@@ -663,7 +666,14 @@ std::string Gen::source() {
         ln("        if (pr) load_chunk(w, pbase);");
         ln("        run_ops(v, base);");
         ln("        if (pr) run_ops(w, pbase);");
-        ln("        __builtin_amdgcn_s_waitcnt(0);");
+        {
+            std::string h = "       ";
+            for (int j = 0; j < NR; ++j) h += fmt(" hold(v[%d]);", j);
+            ln(h);
+            h = "        if (pr) {";
+            for (int j = 0; j < NR; ++j) h += fmt(" hold(w[%d]);", j);
+            ln(h + " }");
+        }
         ln("        __syncthreads();");
         ln("        store_chunk(v, pbase);");
         ln("        if (pr) store_chunk(w, base);");
@@ -679,7 +689,15 @@ std::string Gen::source() {
         ln("        load_chunk(v, base);");
     }
     ln("        run_ops(v, base);");
-    if (relabel) ln("        __syncthreads();");
+    if (relabel) {
+        // a thread may store where another thread of the chunk loaded: every
+        // thread's loads of the tile complete before the barrier (a barrier
+        // alone does not wait for outstanding loads)
+        std::string h = "       ";
+        for (int j = 0; j < NR; ++j) h += fmt(" hold(v[%d]);", j);
+        ln(h);
+        ln("        __syncthreads();");
+    }
     ln("        store_chunk(v, base);");
     if (PF) {
         std::string cp = "       ";

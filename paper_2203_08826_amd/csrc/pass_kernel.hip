@@ -26,6 +26,12 @@ constexpr int PT = 256;
 
 // Workgroup barrier that orders LDS accesses only: outstanding global loads
 // (the next chunk's prefetch) stay in flight across it.
+// An amplitude as an operand of an empty volatile asm: the compiler waits for
+// its load before this point, and the asm is not moved across a barrier.
+template <typename C> __device__ __forceinline__ void hold_value(const C &v) {
+    asm volatile("" ::"v"(v.x), "v"(v.y));
+}
+
 __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
@@ -453,9 +459,13 @@ __global__ void __launch_bounds__(PT) k_pass(typename cplx_of<R>::type *__restri
         {
             // A thread may store to addresses another thread of the chunk
             // loaded (relabelled local bits without an exchange in between):
-            // every load of the chunk must be done (a full barrier waits for
-            // all of this wave's outstanding loads).
-            if (H->relabel) __syncthreads();
+            // every thread's loads of the tile must have completed before
+            // the barrier, which by itself does not wait for them.
+            if (H->relabel) {
+#pragma unroll
+                for (int j = 0; j < NR; ++j) hold_value(v[j]);
+                __syncthreads();
+            }
             const PassPartition &P = parts[cur];
             uint64_t gt = base;
 #pragma unroll

@@ -224,7 +224,8 @@ int launch_bitperm(void *state, int n, int dtype, const std::vector<int> &sigma,
         for (int k = 0; k < L; ++k)
             if (a.lpos[k] == dst) a.lperm[i] = k;
     }
-    const unsigned grid = (unsigned)std::min<uint64_t>(a.nitems, 0x7fffffffull);
+    // fewer than 2^32 threads per launch (HIP's total work-size limit)
+    const unsigned grid = (unsigned)std::min<uint64_t>(a.nitems, 0xffffffffull / BP_THREADS);
     if (dtype == QSV_C64)
         hipLaunchKernelGGL(k_bitperm<float>, dim3(grid), dim3(BP_THREADS), 0, s, (BpC<float> *)state, a);
     else

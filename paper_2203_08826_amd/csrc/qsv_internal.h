@@ -92,13 +92,15 @@ int validate_common(int n, int dtype, const int *targets, int k, const int *cont
 // ---------------------------------------------------------------- device staging
 
 // Per-device staging: a pinned host ring mirrored by a device ring, carved
-// into slots.  A slot carries a HIP event recorded after the last launch
-// that reads it; the slot is reused only after that event completed.
+// into 256 KiB slots.  A slot carries a HIP event recorded after the last
+// launch that reads it; the slot is reused only after that event completed.
+// A request of up to 2 MiB takes consecutive slots.
 struct StagingSlot {
     void *host = nullptr;
     void *dev = nullptr;
     size_t bytes = 0;
-    int index = -1;
+    int index = -1;   // first slot (device * slots + slot)
+    int span = 1;     // consecutive slots held
 };
 
 int staging_acquire(size_t bytes, StagingSlot *slot);          // blocks until free

@@ -89,55 +89,111 @@ static int reduce_grid(uint64_t N) {
 }
 
 // ---------------------------------------------------------------- probabilities
+//
+// out[m] = sum of |psi_i|^2 over the i whose measured bits spell m.  The
+// state is read as rows of 2^w consecutive amplitudes (w = min(6, n)), one
+// per lane of a wave, so every load is a fully used contiguous run whatever
+// qubits are measured.  Bits below w are lane bits, the others row bits.
+// Rows are enumerated as items: the low bits of an item are the unmeasured
+// row bits (ascending positions), the high bits the measured row bits
+// ordered by their place in m (a "job" = one value of them).  Stepping to
+// the next item flips its trailing ones, which flips a fixed set of row
+// bits and of m bits: both updates are one XOR with a table entry (wave
+// uniform, scalar).  A wave takes a contiguous range of items; within a
+// segment (the rows of one job it covers) each lane sums its rows in order,
+// then the unmeasured lane bits are summed by a fixed shuffle butterfly and
+// the lanes with those bits 0 write m's value -- to out directly when every
+// job lies within one wave, else to one slice of a partial array that a
+// second launch adds up in slice order.  The decomposition depends only on
+// n and the measured qubits, so results are reproducible bit for bit.
 
 struct ProbArgs {
-    uint64_t lowmask[QSV_MAX_QUBITS];   // sorted measured bits, for the rest index
-    uint64_t scatter[QSV_MAX_QUBITS];   // bit j of m (LSB first) -> 1 << position
-    int r;
-    int n;
+    uint64_t dbit[QSV_MAX_QUBITS];   // row bit of item bit t
+    uint64_t dlow[QSV_MAX_QUBITS];   // row bits that flip when item bits 0..t flip
+    uint64_t ebit[QSV_MAX_QUBITS];   // m bit of job bit t
+    uint64_t elow[QSV_MAX_QUBITS];   // m bits that flip when job bits 0..t flip
+    uint64_t mlane[64];              // m bits of each lane's own measured lane bits
+    uint64_t nitems;                 // 2^(n - w)
+    uint64_t R;                      // 2^r outcomes
+    int nh, nhu;                     // row bits, unmeasured row bits
+    int w;                           // lane bits
+    int lane_um;                     // mask of the unmeasured lane bits
+    int ipw_log;                     // log2 items (rows) per wave
+    int seg_log;                     // log2 rows per segment
+    int P;                           // slices per job (1: write out directly)
 };
 
-__device__ inline uint64_t prob_index(uint64_t m, uint64_t rest, const ProbArgs &pa) {
-    uint64_t i = rest;
-    for (int b = 0; b < pa.r; ++b) {
-        const uint64_t lo = i & pa.lowmask[b];
-        i = lo | ((i ^ lo) << 1);
-    }
-    for (int j = 0; j < pa.r; ++j)
-        if ((m >> j) & 1) i |= pa.scatter[j];
-    return i;
-}
+constexpr int PB = 8;   // rows loaded per batch by every lane
 
-// Block (m, p) sums the rest indices [p * S, (p + 1) * S) of outcome m.
 template <typename C>
-__global__ void __launch_bounds__(RT) k_probs_partial(const C *__restrict__ psi, ProbArgs pa, uint64_t S, int P,
-                                                      double *part) {
-    __shared__ double sh[RT / 64];
-    const uint64_t m = blockIdx.x / P;
-    const uint64_t p = blockIdx.x % P;
+__global__ void __launch_bounds__(256) k_probs(const C *__restrict__ psi, ProbArgs pa, double *__restrict__ dst) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t wave = (uint64_t)blockIdx.x * 4 + (uint64_t)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t ipw = 1ull << pa.ipw_log;
+    uint64_t item = wave << pa.ipw_log;
+    if (item >= pa.nitems) return;   // the whole wave
+    uint64_t row = 0;
+    for (int t = 0; t < pa.nh; ++t)
+        if ((item >> t) & 1) row ^= pa.dbit[t];
+    uint64_t job = item >> pa.nhu;
+    uint64_t mrow = 0;
+    for (int t = 0; t < pa.nh - pa.nhu; ++t)
+        if ((job >> t) & 1) mrow ^= pa.ebit[t];
+    const bool live = lane < (1 << pa.w);
+    const uint64_t mlane = pa.mlane[lane];
+    const bool leader = live && (lane & pa.lane_um) == 0;
+    const uint64_t segmask = (1ull << pa.seg_log) - 1;
+    const uint64_t slice = pa.P > 1 ? ((item & ((1ull << pa.nhu) - 1)) >> pa.ipw_log) : 0;
     double acc = 0.0;
-    for (uint64_t t = threadIdx.x; t < S; t += RT) acc += abs2d(psi[prob_index(m, p * S + t, pa)]);
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    for (uint64_t k = 0; k < ipw; k += PB) {
+        double v[PB];
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+            v[b] = 0.0;
+            if (k + b < ipw) {
+                if (live) v[b] = abs2d(psi[(row << pa.w) | (uint64_t)lane]);
+                const uint64_t ones = __builtin_ctzll(~item);   // trailing ones of the item
+                if (ones < (uint64_t)pa.nh) row ^= pa.dlow[ones];
+                ++item;
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+            if (k + b >= ipw) break;
+            acc += v[b];
+            if (((k + b + 1) & segmask) == 0) {   // end of a segment (wave uniform)
+                double t = acc;
+#pragma unroll
+                for (int u = 0; u < 6; ++u)
+                    if ((pa.lane_um >> u) & 1) t += __shfl_xor(t, 1 << u, 64);
+                if (leader) dst[slice * pa.R + (mrow | mlane)] = t;
+                acc = 0.0;
+                const uint64_t jo = __builtin_ctzll(~job);
+                if (jo < (uint64_t)(pa.nh - pa.nhu)) mrow ^= pa.elow[jo];
+                ++job;
+            }
+        }
+    }
 }
 
-__global__ void k_probs_finish(const double *part, int P, uint64_t R, double *out) {
+// out[m] = sum over the P slices of part[slice * R + m], in slice order:
+// one thread per outcome for few slices, else one block per outcome.
+__global__ void k_probs_finish_thread(const double *__restrict__ part, uint64_t R, int P, double *__restrict__ out) {
     const uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= R) return;
     double s = 0.0;
-    for (int p = 0; p < P; ++p) s += part[m * P + p];
+    for (int p = 0; p < P; ++p) s += part[(uint64_t)p * R + m];
     out[m] = s;
 }
 
-// Few amplitudes per outcome: one thread per outcome, sequential sum.
-template <typename C>
-__global__ void __launch_bounds__(RT) k_probs_direct(const C *__restrict__ psi, ProbArgs pa, uint64_t R,
-                                                     uint64_t S, double *out) {
-    const uint64_t m = (uint64_t)blockIdx.x * RT + threadIdx.x;
-    if (m >= R) return;
-    double acc = 0.0;
-    for (uint64_t t = 0; t < S; ++t) acc += abs2d(psi[prob_index(m, t, pa)]);
-    out[m] = acc;
+__global__ void __launch_bounds__(RT) k_probs_finish_block(const double *__restrict__ part, uint64_t R, int P,
+                                                           double *__restrict__ out) {
+    __shared__ double sh[RT / 64];
+    const uint64_t m = blockIdx.x;
+    double s = 0.0;
+    for (int p = threadIdx.x; p < P; p += RT) s += part[(uint64_t)p * R + m];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[m] = s;
 }
 
 // ---------------------------------------------------------------- TFIM energy
@@ -245,41 +301,100 @@ static int inner_t(const void *a, const void *b, int n, double *out, hipStream_t
     return QSV_OK;
 }
 
-template <typename C>
-static int probs_t(const void *state, int n, const int *qubits, int r, double *out, hipStream_t s) {
-    ProbArgs pa;
+// Largest partial array of the probabilities reduction (doubles) and the
+// most slices a job is cut into.
+constexpr uint64_t PROB_PART_MAX = 1ull << 16;
+constexpr uint64_t PROB_SLICES_MAX = 4096;
+
+// The decomposition of a probabilities launch (host only; no HIP call).
+int prob_args(int n, const int *qubits, int r, ProbArgs *out) {
+    ProbArgs &pa = *out;
     std::memset(&pa, 0, sizeof(pa));
-    pa.r = r;
-    pa.n = n;
-    std::vector<int> sorted(qubits, qubits + r);
-    std::sort(sorted.begin(), sorted.end());
-    for (int i = 0; i < r; ++i) pa.lowmask[i] = (1ull << sorted[i]) - 1ull;
-    for (int j = 0; j < r; ++j) pa.scatter[r - 1 - j] = 1ull << qubits[j];   // qubits[0] = MSB of m
-    const uint64_t R = 1ull << r, S = 1ull << (n - r);
-    if (S < 4 * RT) {
-        const uint64_t blocks = (R + RT - 1) / RT;
-        hipLaunchKernelGGL((k_probs_direct<C>), dim3((unsigned)blocks), dim3(RT), 0, s, (const C *)state, pa, R, S,
-                           out);
+    const int w = n < 6 ? n : 6;
+    pa.w = w;
+    pa.nh = n - w;
+    pa.R = 1ull << r;
+    int mpos[QSV_MAX_QUBITS];   // m bit of each qubit, -1 if not measured
+    for (int q = 0; q < n; ++q) mpos[q] = -1;
+    for (int j = 0; j < r; ++j) mpos[qubits[j]] = r - 1 - j;
+    for (int q = 0; q < w; ++q)
+        if (mpos[q] < 0) pa.lane_um |= 1 << q;
+    for (int l = 0; l < 64; ++l)
+        for (int q = 0; q < w; ++q)
+            if (mpos[q] >= 0 && ((l >> q) & 1)) pa.mlane[l] |= 1ull << mpos[q];
+    // item bits: unmeasured row bits (ascending), then measured row bits by m bit
+    int t = 0;
+    for (int q = w; q < n; ++q)
+        if (mpos[q] < 0) pa.dbit[t++] = 1ull << (q - w);
+    pa.nhu = t;
+    for (int mb = 0; mb < r; ++mb)
+        for (int q = w; q < n; ++q)
+            if (mpos[q] == mb) {
+                pa.ebit[t - pa.nhu] = 1ull << mb;
+                pa.dbit[t++] = 1ull << (q - w);
+            }
+    uint64_t d = 0, e = 0;
+    for (int b = 0; b < pa.nh; ++b) {
+        d ^= pa.dbit[b];
+        pa.dlow[b] = d;
+    }
+    for (int b = 0; b < pa.nh - pa.nhu; ++b) {
+        e ^= pa.ebit[b];
+        pa.elow[b] = e;
+    }
+    pa.nitems = 1ull << pa.nh;
+    const uint64_t RS = 1ull << pa.nhu;   // rows of one job
+    // items per wave: at most 2^17 waves, at least one batch where possible
+    uint64_t ipw = pa.nitems >> 17;
+    if (ipw < PB) ipw = PB;
+    if (ipw > pa.nitems) ipw = pa.nitems;
+    uint64_t P = 1;
+    if (ipw < RS) {
+        P = RS / ipw;
+        uint64_t pmax = PROB_PART_MAX / pa.R;
+        if (pmax > PROB_SLICES_MAX) pmax = PROB_SLICES_MAX;
+        if (pmax < 1) pmax = 1;
+        if (P > pmax) {
+            P = pmax;
+            ipw = RS / P;
+        }
+    }
+    pa.P = (int)P;
+    pa.ipw_log = __builtin_ctzll(ipw);
+    pa.seg_log = __builtin_ctzll(ipw < RS ? ipw : RS);
+    return QSV_OK;
+}
+
+// `fixed_part`: a partial array of PROB_PART_MAX doubles to use instead of a
+// staging slot (NULL: a staging slot).
+template <typename C>
+static int probs_t(const void *state, int n, const int *qubits, int r, double *out, hipStream_t s,
+                   double *fixed_part) {
+    ProbArgs pa;
+    prob_args(n, qubits, r, &pa);
+    const uint64_t waves = pa.nitems >> pa.ipw_log;
+    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    if (pa.P == 1) {
+        hipLaunchKernelGGL((k_probs<C>), dim3(blocks), dim3(256), 0, s, (const C *)state, pa, out);
         QSV_HIP_CHECK(hipGetLastError());
         return QSV_OK;
     }
-    // parts per outcome: aim at >= 8 blocks per CU, each summing >= 4 * RT amplitudes
-    uint64_t P = ((uint64_t)device_sm_count() * 8 + R - 1) / R;
-    while (P > 1 && S / P < 4 * RT) P >>= 1;
-    uint64_t p2 = 1;
-    while (p2 * 2 <= P) p2 <<= 1;   // power of two, so P divides S
-    P = p2;
-    const size_t bytes = sizeof(double) * R * P;
-    if (bytes > staging_slot_bytes()) return fail(QSV_ERR_UNSUPPORTED, "probabilities: too many outcomes for one launch");
+    if (pa.R * (uint64_t)pa.P > PROB_PART_MAX) return fail(QSV_ERR_ARG, "internal: partial array above its bound");
     StagingSlot slot;
-    int st = staging_acquire(bytes, &slot);
-    if (st) return st;
-    double *part = (double *)slot.dev;
-    hipLaunchKernelGGL((k_probs_partial<C>), dim3((unsigned)(R * P)), dim3(RT), 0, s, (const C *)state, pa, S / P,
-                       (int)P, part);
-    hipLaunchKernelGGL(k_probs_finish, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, part, (int)P, R, out);
+    double *part = fixed_part;
+    if (!part) {
+        int st = staging_acquire(sizeof(double) * pa.R * pa.P, &slot);
+        if (st) return st;
+        part = (double *)slot.dev;
+    }
+    hipLaunchKernelGGL((k_probs<C>), dim3(blocks), dim3(256), 0, s, (const C *)state, pa, part);
+    if (pa.P >= 64)
+        hipLaunchKernelGGL(k_probs_finish_block, dim3((unsigned)pa.R), dim3(RT), 0, s, part, pa.R, pa.P, out);
+    else
+        hipLaunchKernelGGL(k_probs_finish_thread, dim3((unsigned)((pa.R + 255) / 256)), dim3(256), 0, s, part, pa.R,
+                           pa.P, out);
     hipError_t e = hipGetLastError();
-    staging_release(slot, s);
+    if (!fixed_part) staging_release(slot, s);
     if (e != hipSuccess) return hip_fail(e, "probabilities launch");
     return QSV_OK;
 }
@@ -366,8 +481,8 @@ int qsv_probabilities(const void *state, int n, int dtype, const int *qubits, in
         if (seen & (1ull << qubits[j])) return fail(QSV_ERR_QUBIT_DUP, "measured qubit repeats");
         seen |= 1ull << qubits[j];
     }
-    return dtype == QSV_C64 ? probs_t<float2>(state, n, qubits, r, out_dev, (hipStream_t)stream)
-                            : probs_t<double2>(state, n, qubits, r, out_dev, (hipStream_t)stream);
+    return dtype == QSV_C64 ? probs_t<float2>(state, n, qubits, r, out_dev, (hipStream_t)stream, nullptr)
+                            : probs_t<double2>(state, n, qubits, r, out_dev, (hipStream_t)stream, nullptr);
 }
 
 int qsv_expval_zz_x(const void *state, int n, int dtype, double J, double h, int periodic, double *out_dev,

@@ -45,7 +45,8 @@ def test_probabilities(gpu, dt, n):
         qs = [int(q) for q in rng.permutation(n)[:r]]
         got = qsv.qsv_probabilities(d, qs).cpu().numpy()
         want = S.probabilities(psi, qs)
-        assert np.max(np.abs(got - want)) <= 1e-14, (r, qs)
+        # 2^(n-r) non-negative float64 terms summed in two orders
+        assert np.max(np.abs(got - want)) <= 2.0 ** (n - r + 1 - 53) + 1e-16, (r, qs)
         assert abs(got.sum() - S.norm2(psi)) <= 1e-12
 
 

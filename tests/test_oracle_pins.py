@@ -226,6 +226,11 @@ def test_infidelity():
     phi = W.random_state(6, 2)
     want = 1 - abs(np.vdot(psi, phi)) ** 2
     assert abs(S.infidelity(psi, phi) - want) <= 1e-15
+    # unnormalised inputs: the norms divide out (hand-computed cases)
+    assert S.infidelity(np.array([1.0, 0.0]), np.array([1.0, 1.0])) == 0.5
+    assert S.infidelity(np.array([2.0, 0.0]), np.array([0.0, 3.0j])) == 1.0
+    assert abs(S.infidelity(np.array([1.0, 1.0j]), np.array([3.0, 3.0j]))) <= 1e-15
+    assert abs(S.infidelity(3.0 * psi, 0.5 * phi) - want) <= 1e-14
 
 
 # ------------------------------------------------------------ fusion (Sec. 3.2)
@@ -287,6 +292,22 @@ def test_planted_adjoint_sign_error_is_caught():
 def _mlp(rng, sizes):
     return [(rng.standard_normal((a, b)) / math.sqrt(a), 0.1 * rng.standard_normal(b))
             for a, b in zip(sizes[:-1], sizes[1:])]
+
+
+def test_mlp_forward_hand_computed():
+    """A 2 -> 2 -> 1 network evaluated by hand: ReLU on the hidden layer only,
+    x @ W with W stored [fan_in, fan_out]."""
+    params = [(np.array([[1.0, -2.0], [3.0, 1.0]]), np.array([0.5, -1.0])),
+              (np.array([[2.0], [-1.0]]), np.array([0.25]))]
+    X = np.array([[1.0, 1.0], [2.0, -1.0], [-1.0, 0.0]])
+    # row 1: hidden [4.5, -2] -> [4.5, 0] -> 9 + 0.25
+    # row 2: hidden [-0.5, -6] -> [0, 0] -> 0.25
+    # row 3: hidden [-0.5, 1] -> [0, 1] -> -1 + 0.25 (a negative output: no ReLU on it)
+    pred, (acts, pre) = M.forward(params, X)
+    assert np.array_equal(pred, [9.25, 0.25, -0.75])
+    assert np.array_equal(pre[0], [[4.5, -2.0], [-0.5, -6.0], [-0.5, 1.0]])
+    assert np.array_equal(acts[1], [[4.5, 0.0], [0.0, 0.0], [0.0, 1.0]])
+    assert M.mse(pred, np.array([9.25, 1.25, 0.25])) == 2.0 / 3.0
 
 
 def test_mlp_backward_matches_finite_differences():
