@@ -265,6 +265,45 @@ int qsv_expval_zz_x(const void *state, int n, int dtype, double J, double h, int
 int qsv_apply_tfim(const void *state, void *out, int n, int dtype, double J, double h,
                    int periodic, void *stream);
 
+/* ------------------------------------------------------------------ measurement
+ * The methodology section (Sec. 2) provides, besides the measurement
+ * probabilities, an operator that collapses a state onto a measured outcome
+ * and re-normalises it, and shot frequencies sampled with the Metropolis
+ * algorithm.  Outcome indices follow qsv_probabilities (qubits[0] = most
+ * significant bit).  Random numbers are inputs: the same inputs give the
+ * same samples. */
+
+/* Collapse onto outcome m of the r measured qubits, in place:
+ * psi_i <- psi_i / sqrt(p) where the measured bits of i spell m, 0 elsewhere,
+ * with p = ||P_m psi||^2 summed in float64 in a fixed order.  When p = 0 every
+ * amplitude becomes 0.  prob_dev (device, may be NULL) receives p.
+ * 1 <= r <= n, m < 2^r (else QSV_ERR_ARG). */
+int qsv_collapse(void *state, int n, int dtype, const int *qubits, int r, uint64_t outcome,
+                 double *prob_dev, void *stream);
+
+/* Inverse-CDF shot sampling from R = 2^r outcome probabilities (device
+ * float64, need not sum to 1).  cdf_dev (device, R doubles, caller-owned)
+ * receives c_m = p_0 + ... + p_m, summed in a fixed order; shot s with
+ * uniform u_s in [0, 1) (uniforms_dev, nshots doubles) is the smallest m
+ * with u_s c_{R-1} < c_m (the last outcome of non-zero probability if none);
+ * an outcome of probability 0 is never drawn.  samples_dev (nshots int64) and
+ * counts_dev (R uint64, zeroed by the call, then the frequency of each
+ * outcome) are optional outputs; either may be NULL.  1 <= r <= 40. */
+int qsv_sample_cdf(const double *probs_dev, int r, const double *uniforms_dev, int64_t nshots,
+                   double *cdf_dev, int64_t *samples_dev, uint64_t *counts_dev, void *stream);
+
+/* Metropolis shot frequencies (Metropolis et al. 1953): nchains independent
+ * chains.  Chain c starts at outcome starts_dev[c]; at step s it proposes
+ * y = proposals_dev[s * nchains + c] and moves there when
+ * uniforms_dev[s * nchains + c] * p(x) < p(y), x the outcome it holds
+ * (acceptance min(1, p(y)/p(x)) for a symmetric proposal); after every step
+ * it counts x.  counts_dev (R uint64) is zeroed by the call and receives
+ * the frequencies (nchains * steps in all).  All arrays are device memory.
+ * Proposals outside [0, R) are rejected and starts outside it begin at 0. */
+int qsv_sample_metropolis(const double *probs_dev, int r, const int64_t *starts_dev,
+                          const int64_t *proposals_dev, const double *uniforms_dev, int nchains,
+                          int64_t steps, uint64_t *counts_dev, void *stream);
+
 /* ------------------------------------------------------------------ adjoint
  * Adjoint-method gradient of E = <psi|H|psi> (Jones and Gacon,
  * arXiv:2009.02823).  On entry psi holds U_L..U_1 psi_0 and lam holds H psi.

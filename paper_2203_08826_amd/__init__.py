@@ -364,6 +364,68 @@ def qsv_apply_tfim(state, out, J=1.0, h=0.5, periodic=False, stream=None):
     return out
 
 
+# ------------------------------------------------------------------ measurement
+
+def _dptr(t, dtype, count, what):
+    torch = _torch()
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or t.numel() < count:
+        raise ValueError("%s must be a contiguous device tensor of %s with >= %d elements" % (what, dtype, count))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def qsv_collapse(state, qubits, outcome, prob_out=None, stream=None):
+    """Collapse `state` in place onto `outcome` of `qubits`; returns a device
+    float64 tensor holding the outcome's probability before re-normalisation."""
+    torch = _torch()
+    p, n, dt = _state(state)
+    q, r = _ints(qubits)
+    prob_out = _dev_out((1,), prob_out)
+    check("qsv_collapse", load().qsv_collapse(p, n, dt, q, r, int(outcome), ctypes.c_void_p(prob_out.data_ptr()),
+                                              _stream(stream)))
+    return prob_out
+
+
+def qsv_sample_cdf(probs, uniforms, cdf=None, samples=True, counts=True, stream=None):
+    """Inverse-CDF samples of `probs` (device float64, 2^r) for device float64
+    `uniforms`; returns (cdf, samples or None, counts or None)."""
+    torch = _torch()
+    R = probs.numel()
+    r = R.bit_length() - 1
+    if R < 2 or R != 1 << r:
+        raise ValueError("probs must hold 2^r entries, r >= 1")
+    ns = uniforms.numel()
+    cdf = cdf if cdf is not None else torch.empty(R, dtype=torch.float64, device=probs.device)
+    sm = torch.empty(ns, dtype=torch.int64, device=probs.device) if samples else None
+    ct = torch.empty(R, dtype=torch.uint64, device=probs.device) if counts else None
+    check("qsv_sample_cdf", load().qsv_sample_cdf(
+        _dptr(probs, torch.float64, R, "probs"), r, _dptr(uniforms, torch.float64, ns, "uniforms"), ns,
+        _dptr(cdf, torch.float64, R, "cdf"), _dptr(sm, torch.int64, ns, "samples"),
+        _dptr(ct, torch.uint64, R, "counts"), _stream(stream)))
+    return cdf, sm, ct
+
+
+def qsv_sample_metropolis(probs, starts, proposals, uniforms, stream=None):
+    """Metropolis frequencies: `starts` [C] int64, `proposals` [steps, C]
+    int64, `uniforms` [steps, C] float64 (device); returns counts [2^r] uint64."""
+    torch = _torch()
+    R = probs.numel()
+    r = R.bit_length() - 1
+    if R < 2 or R != 1 << r:
+        raise ValueError("probs must hold 2^r entries, r >= 1")
+    C = starts.numel()
+    steps = proposals.shape[0] if proposals.dim() == 2 else 0
+    if proposals.numel() != steps * C or uniforms.numel() != steps * C:
+        raise ValueError("proposals and uniforms must be [steps, chains]")
+    counts = torch.empty(R, dtype=torch.uint64, device=probs.device)
+    check("qsv_sample_metropolis", load().qsv_sample_metropolis(
+        _dptr(probs, torch.float64, R, "probs"), r, _dptr(starts, torch.int64, C, "starts"),
+        _dptr(proposals, torch.int64, steps * C, "proposals"), _dptr(uniforms, torch.float64, steps * C, "uniforms"),
+        C, steps, _dptr(counts, torch.uint64, R, "counts"), _stream(stream)))
+    return counts
+
+
 # ------------------------------------------------------------------ adjoint
 
 def qsv_adjoint_grad(psi, lam, circuit, out=None, stream=None):

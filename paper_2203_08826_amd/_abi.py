@@ -83,6 +83,9 @@ SIGNATURES = {
     "qsv_inner": ([_vp, _vp, _i, _i, _vp, _vp], _i),
     "qsv_expval_zz_x": ([_vp, _i, _i, _d, _d, _i, _vp, _vp], _i),
     "qsv_apply_tfim": ([_vp, _vp, _i, _i, _d, _d, _i, _vp], _i),
+    "qsv_collapse": ([_vp, _i, _i, _vp, _i, ctypes.c_uint64, _vp, _vp], _i),
+    "qsv_sample_cdf": ([_vp, _i, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp], _i),
+    "qsv_sample_metropolis": ([_vp, _i, _vp, _vp, _vp, _i, ctypes.c_int64, _vp, _vp], _i),
     "qsv_adjoint_grad": ([_vp, _vp, _i, _i, _vp, _i, _vp, _vp], _i),
     "qsv_mlp_forward": ([_vp, _vp, _i, _vp, _i, _vp, _vp, _vp], _i),
     "qsv_mlp_backward": ([_vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp], _i),
