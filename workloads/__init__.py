@@ -119,6 +119,41 @@ def variational(n, layers, seed=0):
     return c
 
 
+def adiabatic_trotter(n, T, dt, h=1.0, periodic=True, order=2):
+    """Trotterised adiabatic evolution (Sec. 3.3) as a circuit of one- and
+    two-qubit gates.  H(s) = (1 - s) H0 + s H1 with H0 = -sum X_i and the
+    transverse-field Ising model H1 = -sum Z_i Z_{i+1} - h sum X_i (periodic
+    for n > 2), s = t / T, each step at its midpoint s_k = (k + 1/2) dt / T.
+    H(s) = -a(s) sum X_i - b(s) sum Z_i Z_{i+1}, a = 1 - s + s h, b = s.
+
+    One step of the second-order (symmetric) decomposition is
+    exp(i a dt/2 sum X) exp(i b dt sum ZZ) exp(i a dt/2 sum X); first order
+    drops the second half-step of X.  exp(i c X) is RX(-2c); exp(i c Z Z) is
+    the diagonal gate diag(e^{ic}, e^{-ic}, e^{-ic}, e^{ic}).  Consecutive X
+    half-steps of neighbouring time steps are kept as separate gates.  The
+    initial state |+>^n is not part of the circuit."""
+    steps = int(round(T / dt))
+    pairs = [(q, q + 1) for q in range(n - 1)]
+    if periodic and n > 2:
+        pairs.append((n - 1, 0))
+    c = []
+    for k in range(steps):
+        s = (k + 0.5) * dt / T
+        a, b = 1.0 - s + s * h, s
+        xa = a * dt / 2 if order == 2 else a * dt
+        for q in range(n):
+            c.append(gate("RX", [q], [], [-2.0 * xa]))
+        ph = b * dt
+        for i, j in pairs:
+            g = gate("DIAG", [i, j])
+            g["diag"] = np.exp(1j * ph * np.array([1.0, -1.0, -1.0, 1.0]))
+            c.append(g)
+        if order == 2:
+            for q in range(n):
+                c.append(gate("RX", [q], [], [-2.0 * xa]))
+    return c
+
+
 def parameter_slots(circuit):
     """Indices of gates that carry a trainable angle (RX/RY/RZ), in order."""
     return [i for i, g in enumerate(circuit) if g["name"] in ("RX", "RY", "RZ")]
