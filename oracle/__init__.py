@@ -21,6 +21,10 @@ What is here, each written from the paper's statement of the problem:
 * ``mlp``: float64 numpy forward/backward/Adam of the fusion cost model.
 * ``measure``: collapse and re-normalisation onto a measurement outcome,
   inverse-CDF shot sampling and Metropolis shot frequencies (Sec. 2).
+* ``evolution``: adiabatic evolution by exponentiating the dense Hamiltonian
+  at every step (Sec. 3.3).
+* ``density``: density matrices, U rho U^dagger with full operators, Kraus
+  channels, probabilities of the diagonal (Sec. 2).
 
 Every function states the passage it follows.  Functions with nothing but the
 code itself to check them against say "parity unpinned".
