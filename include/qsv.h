@@ -253,6 +253,17 @@ int qsv_run_pass(void *state, int n, int dtype, const qsv_gate *gates, int ngate
  * 1 <= r <= n. */
 int qsv_probabilities(const void *state, int n, int dtype, const int *qubits, int r,
                       double *out_dev, void *stream);
+/* qsv_probabilities for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and result, bit for bit, but the partial sums live in a fixed
+ * 512 KiB device array of the library (one per GPU, kept until the process
+ * ends) instead of the staging ring, so the call allocates nothing -- not
+ * even on its first use.  Every call on a GPU shares that array: calls that
+ * overlap on one GPU (different streams, or different host threads) race
+ * and must be serialised by the caller.  Arguments, limits and errors as for
+ * qsv_probabilities (the decomposition never needs more than the array). */
+int qsv_probabilities_noalloc(const void *state, int n, int dtype, const int *qubits, int r,
+                              double *out_dev, void *stream);
 /* out_dev[0] = <psi|psi>. */
 int qsv_norm2(const void *state, int n, int dtype, double *out_dev, void *stream);
 /* out_dev[0..1] = re, im of <a|b> = sum conj(a_i) b_i. */

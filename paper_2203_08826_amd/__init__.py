@@ -329,6 +329,20 @@ def qsv_probabilities(state, qubits, out=None, stream=None):
     return out
 
 
+def qsv_probabilities_noalloc(state, qubits, out, stream=None):
+    """qsv_probabilities without any allocation inside the library; `out`
+    (float64 device tensor of 2^r entries) must be supplied."""
+    torch = _torch()
+    p, n, dt = _state(state)
+    q, r = _ints(qubits)
+    if out is None:
+        raise ValueError("out must be supplied (this call allocates nothing)")
+    out = _dev_out((1 << r,), out)
+    check("qsv_probabilities_noalloc", load().qsv_probabilities_noalloc(
+        p, n, dt, q, r, ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
 def qsv_norm2(state, out=None, stream=None):
     p, n, dt = _state(state)
     out = _dev_out((1,), out)

@@ -79,6 +79,7 @@ SIGNATURES = {
     "qsv_apply_block": ([_vp, _i, _i, _vp, _vp, _i, _vp], _i),
     "qsv_run_pass": ([_vp, _i, _i, _vp, _i, _vp, _i, _vp], _i),
     "qsv_probabilities": ([_vp, _i, _i, _vp, _i, _vp, _vp], _i),
+    "qsv_probabilities_noalloc": ([_vp, _i, _i, _vp, _i, _vp, _vp], _i),
     "qsv_norm2": ([_vp, _i, _i, _vp, _vp], _i),
     "qsv_inner": ([_vp, _vp, _i, _i, _vp, _vp], _i),
     "qsv_expval_zz_x": ([_vp, _i, _i, _d, _d, _i, _vp, _vp], _i),

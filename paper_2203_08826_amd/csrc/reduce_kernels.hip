@@ -9,6 +9,8 @@
 // write one partial each, and a second launch adds the partials in order.
 // The grid depends only on the problem size and the device's CU count, so a
 // result is reproducible bit for bit on a given device.
+#include <mutex>
+
 #include "qsv_internal.h"
 
 namespace qsv {
@@ -399,6 +401,36 @@ static int probs_t(const void *state, int n, const int *qubits, int r, double *o
     return QSV_OK;
 }
 
+// ---------------------------------------------------------------- no-allocation variant
+//
+// qsv_probabilities_noalloc keeps its partial sums in this file-scope device
+// array (one copy per GPU, held until the process ends) instead of the
+// staging ring, so it never allocates.  Host code reaches the array only
+// through the device address hipGetSymbolAddress returns for the current
+// device, looked up once per device.
+
+static __device__ __align__(256) double scratch[PROB_PART_MAX];
+
+namespace {
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[64] = {nullptr};
+}  // namespace
+
+static int scratch_address(double **out) {
+    int dev = 0;
+    QSV_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(QSV_ERR_ARG, "device index above 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        QSV_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(QSV_ERR_HIP, "no device address for the probabilities scratch array");
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return QSV_OK;
+}
+
 template <typename C>
 static int tfim_t(const void *state, int n, double J, double h, int periodic, double *out, hipStream_t s) {
     TfimArgs a;
@@ -483,6 +515,24 @@ int qsv_probabilities(const void *state, int n, int dtype, const int *qubits, in
     }
     return dtype == QSV_C64 ? probs_t<float2>(state, n, qubits, r, out_dev, (hipStream_t)stream, nullptr)
                             : probs_t<double2>(state, n, qubits, r, out_dev, (hipStream_t)stream, nullptr);
+}
+
+int qsv_probabilities_noalloc(const void *state, int n, int dtype, const int *qubits, int r, double *out_dev,
+                              void *stream) {
+    int st = check_red(state, n, dtype, out_dev);
+    if (st) return st;
+    if (r < 1 || r > n) return fail(QSV_ERR_ARITY, "number of measured qubits must be in [1, n]");
+    if (!qubits) return fail(QSV_ERR_NULL, "qubits is NULL");
+    uint64_t seen = 0;
+    for (int j = 0; j < r; ++j) {
+        if (qubits[j] < 0 || qubits[j] >= n) return fail(QSV_ERR_QUBIT_RANGE, "measured qubit out of range");
+        if (seen & (1ull << qubits[j])) return fail(QSV_ERR_QUBIT_DUP, "measured qubit repeats");
+        seen |= 1ull << qubits[j];
+    }
+    double *part = nullptr;
+    if ((st = scratch_address(&part))) return st;
+    return dtype == QSV_C64 ? probs_t<float2>(state, n, qubits, r, out_dev, (hipStream_t)stream, part)
+                            : probs_t<double2>(state, n, qubits, r, out_dev, (hipStream_t)stream, part);
 }
 
 int qsv_expval_zz_x(const void *state, int n, int dtype, double J, double h, int periodic, double *out_dev,
