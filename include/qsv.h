@@ -115,6 +115,11 @@ int qsv_apply_diagonal(void *state, int n, int dtype, const void *diag,
  * on {|01>, |10>}, e^{-i phi} on |11> (t0 = most significant). */
 int qsv_apply_fsim(void *state, int n, int dtype, int t0, int t1, double theta, double phi, void *stream);
 
+/* psi <- (re + i im) psi for every amplitude: normalisation and global
+ * phases.  Also the plain in-place stream (one read and one write of the
+ * state) that the gate kernels are measured against. */
+int qsv_scale(void *state, int n, int dtype, double re, double im, void *stream);
+
 /* ------------------------------------------------------------------ circuits
  * A circuit is an array of qsv_gate.  Named kinds build their matrix from
  * params; QSV_GATE_MATRIX and QSV_GATE_DIAG read `data` (host complex128,
@@ -169,6 +174,14 @@ typedef struct qsv_plan_options {
                         * fixed at compile time; results equal the interpreted
                         * pass kernel's up to rounding (matrix and phase entries
                         * within 2^-50 of 0 or +-1 are taken as exact).
+                        * 2: compiled as for 1, but parametric: gate matrix
+                        * entries and phase angles are read from the pass
+                        * program at run time instead of compiled in, so a
+                        * kernel depends only on the circuit's structure;
+                        * plans of circuits that differ only in their angles
+                        * (a parameter sweep) share compiled kernels, and a
+                        * plan with the same structure as an earlier one in
+                        * the process compiles nothing.
                         * 0: interpreted. */
 } qsv_plan_options;
 
@@ -314,6 +327,35 @@ int qsv_sample_cdf(const double *probs_dev, int r, const double *uniforms_dev, i
 int qsv_sample_metropolis(const double *probs_dev, int r, const int64_t *starts_dev,
                           const int64_t *proposals_dev, const double *uniforms_dev, int nchains,
                           int64_t steps, uint64_t *counts_dev, void *stream);
+
+/* ------------------------------------------------------------------ density matrices
+ * The methodology section applies Eq. 1 to density matrices as well.  rho of
+ * n qubits (1 <= n <= 20) is a device array of 2^(2n) complex numbers,
+ * row-major: rho[r, c] at index r * 2^n + c, i.e. a 2n-qubit vector whose
+ * column qubit q is bit q and whose row qubit q is bit q + n. */
+
+/* A plan that applies every gate of the circuit as rho -> G rho G^dagger:
+ * G on the row bits (targets and controls + n) and conj(G) on the column
+ * bits.  The result is a plan over 2n qubits with twice the gates (row copy
+ * then column copy of each gate, in circuit order), built and run exactly
+ * as qsv_plan_create / qsv_plan_execute build and run a 2n-qubit circuit;
+ * gate indices reported by the plan refer to that doubled circuit.  Gates
+ * are validated on n qubits. */
+int qsv_dm_plan_create(int n, int dtype, const qsv_gate *gates, int ngates, const qsv_plan_options *opts,
+                       qsv_plan **out);
+/* A one-qubit channel rho -> sum_k K_k rho K_k^dagger on qubit `target`:
+ * `kraus` holds nk (1..16) host 2x2 complex128 matrices, row-major, one after
+ * another.  Applied in place as the 4x4 superoperator on the (row, column)
+ * bits of the qubit.  Trace preservation is the caller's choice (sum K^dag K
+ * = I); it is not checked. */
+int qsv_dm_apply_channel(void *rho, int n, int dtype, const double *kraus, int nk, int target, void *stream);
+/* out_dev[0..1] = re, im of the trace, float64, fixed order. */
+int qsv_dm_trace(const void *rho, int n, int dtype, double *out_dev, void *stream);
+/* Measurement probabilities from the diagonal: out_dev[m] = sum of
+ * Re rho[i, i] over i whose measured bits spell m (qubits[0] = most
+ * significant bit of m), float64, 2^r entries, 1 <= r <= n. */
+int qsv_dm_probabilities(const void *rho, int n, int dtype, const int *qubits, int r, double *out_dev,
+                         void *stream);
 
 /* ------------------------------------------------------------------ adjoint
  * Adjoint-method gradient of E = <psi|H|psi> (Jones and Gacon,

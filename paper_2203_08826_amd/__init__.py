@@ -167,6 +167,13 @@ def qsv_apply_fsim(state, t0, t1, theta, phi, stream=None):
 
 # ------------------------------------------------------------------ circuits
 
+def qsv_scale(state, factor, stream=None):
+    """state <- factor * state (complex factor), in place."""
+    p, n, dt = _state(state)
+    f = complex(factor)
+    check("qsv_scale", load().qsv_scale(p, n, dt, f.real, f.imag, _stream(stream)))
+
+
 def gates_to_c(circuit):
     """Array of qsv_gate for a list of gate dicts, plus the host buffers it points to."""
     arr = (QsvGate * max(1, len(circuit)))()
@@ -438,6 +445,51 @@ def qsv_sample_metropolis(probs, starts, proposals, uniforms, stream=None):
         _dptr(proposals, torch.int64, steps * C, "proposals"), _dptr(uniforms, torch.float64, steps * C, "uniforms"),
         C, steps, _dptr(counts, torch.uint64, R, "counts"), _stream(stream)))
     return counts
+
+
+# ------------------------------------------------------------------ density matrices
+
+def _dm(rho):
+    """(pointer, n, dtype) of a density matrix tensor of 2^(2n) entries."""
+    p, n2, dt = _state(rho)
+    if n2 % 2:
+        raise ValueError("a density matrix holds 2^(2n) entries")
+    return p, n2 // 2, dt
+
+
+def qsv_dm_plan_create(n, dtype, circuit, mode=PLAN_PER_GATE, kmax=2, local_bits=0, use_mfma=1, jit=0):
+    """Plan applying `circuit` to an n-qubit density matrix (rho -> G rho G^dag);
+    run it with qsv_plan_execute on the 2^(2n)-entry rho."""
+    arr, keep = gates_to_c(circuit)
+    opts = QsvPlanOptions(int(mode), int(kmax), int(local_bits), int(use_mfma), int(jit))
+    h = ctypes.c_void_p()
+    check("qsv_dm_plan_create", load().qsv_dm_plan_create(int(n), int(dtype), arr, len(circuit), ctypes.byref(opts),
+                                                          ctypes.byref(h)))
+    del keep
+    return Plan(h, 2 * len(circuit))
+
+
+def qsv_dm_apply_channel(rho, kraus, target, stream=None):
+    p, n, dt = _dm(rho)
+    k = np.ascontiguousarray(np.asarray(kraus, dtype=np.complex128).reshape(-1, 2, 2))
+    check("qsv_dm_apply_channel", load().qsv_dm_apply_channel(p, n, dt, k.ctypes.data, k.shape[0], int(target),
+                                                              _stream(stream)))
+
+
+def qsv_dm_trace(rho, out=None, stream=None):
+    p, n, dt = _dm(rho)
+    out = _dev_out((2,), out)
+    check("qsv_dm_trace", load().qsv_dm_trace(p, n, dt, ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def qsv_dm_probabilities(rho, qubits, out=None, stream=None):
+    p, n, dt = _dm(rho)
+    q, r = _ints(qubits)
+    out = _dev_out((1 << r,), out)
+    check("qsv_dm_probabilities", load().qsv_dm_probabilities(p, n, dt, q, r, ctypes.c_void_p(out.data_ptr()),
+                                                              _stream(stream)))
+    return out
 
 
 # ------------------------------------------------------------------ adjoint

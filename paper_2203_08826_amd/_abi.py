@@ -65,6 +65,7 @@ SIGNATURES = {
     "qsv_apply_phase": ([_vp, _i, _i, _i, _d, _vp, _i, _vp], _i),
     "qsv_apply_diagonal": ([_vp, _i, _i, _vp, _vp, _i, _vp, _i, _vp], _i),
     "qsv_apply_fsim": ([_vp, _i, _i, _i, _i, _d, _d, _vp], _i),
+    "qsv_scale": ([_vp, _i, _i, _d, _d, _vp], _i),
     "qsv_gate_matrix": ([_vp, _vp], _i),
     "qsv_plan_create": ([_i, _i, _vp, _i, _vp, _vp], _i),
     "qsv_plan_stats_get": ([_vp, _vp], _i),
@@ -87,6 +88,10 @@ SIGNATURES = {
     "qsv_collapse": ([_vp, _i, _i, _vp, _i, ctypes.c_uint64, _vp, _vp], _i),
     "qsv_sample_cdf": ([_vp, _i, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp], _i),
     "qsv_sample_metropolis": ([_vp, _i, _vp, _vp, _vp, _i, ctypes.c_int64, _vp, _vp], _i),
+    "qsv_dm_plan_create": ([_i, _i, _vp, _i, _vp, _vp], _i),
+    "qsv_dm_apply_channel": ([_vp, _i, _i, _vp, _i, _i, _vp], _i),
+    "qsv_dm_trace": ([_vp, _i, _i, _vp, _vp], _i),
+    "qsv_dm_probabilities": ([_vp, _i, _i, _vp, _i, _vp, _vp], _i),
     "qsv_adjoint_grad": ([_vp, _vp, _i, _i, _vp, _i, _vp, _vp], _i),
     "qsv_mlp_forward": ([_vp, _vp, _i, _vp, _i, _vp, _vp, _vp], _i),
     "qsv_mlp_backward": ([_vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp], _i),

@@ -471,4 +471,12 @@ int qsv_apply_diagonal(void *state, int n, int dtype, const void *diag, const in
     return apply_c128_block(state, n, dtype, G.data(), targets, k, controls, c, stream);
 }
 
+int qsv_scale(void *state, int n, int dtype, double re, double im, void *stream) {
+    if (dtype != QSV_C64 && dtype != QSV_C128) return fail(QSV_ERR_DTYPE, "dtype must be QSV_C64 or QSV_C128");
+    if (n < 1 || n > QSV_MAX_QUBITS) return fail(QSV_ERR_NQUBITS, "n must be in [1, 40]");
+    int st = check_state(state);
+    if (st) return st;
+    return launch_scale(state, n, dtype, re, im, (hipStream_t)stream);
+}
+
 }  // extern "C"

@@ -73,7 +73,9 @@ __device__ inline uint64_t group_base(uint64_t g, const GroupArgs &ga) {
 // one unit per thread.
 template <typename C, int M> struct Unroll { static constexpr int U = (sizeof(C) == 8 && M <= 2) ? 4 : 1; };
 // Diagonal gates on 16-byte complex64 members stream best with one unit per
-// thread (30 qubits: Z 5.5 -> 6.0 TB/s, controlled phase 5.6 -> 5.9).
+// thread (30 qubits: Z 5.5 -> 6.0 TB/s, controlled phase 5.6 -> 5.9), with
+// ordinary accesses: they touch runs of a line (Z on qubit 5: 256 bytes of
+// every 512), where nontemporal ones ran slower (Z 6.06 -> 5.59 TB/s).
 template <typename C, int M, int VG> struct DiagUnroll {
     static constexpr int U = (VG == 2 && sizeof(C) == 8) ? 1 : Unroll<C, M>::U;
 };
@@ -81,30 +83,34 @@ template <typename C, int M, int VG> struct DiagUnroll {
 // The VG consecutive amplitudes of one member of a unit as one access: a
 // 16-byte vector for VG = 2 complex64 groups (the element index is even,
 // see above).  Written out because the compiler leaves the predicated loads
-// of several units as 8-byte accesses.
-struct alignas(16) F4 {
-    float a, b, c, d;
-};
-template <typename C, int VG> __device__ __forceinline__ void ld_vg(const C *p, C (&out)[VG]) {
+// of several units as 8-byte accesses.  These complex64 accesses are
+// nontemporal: every amplitude is touched once per gate, and streaming past
+// the caches lifts an in-place 16-byte stream from 5.9 to 6.6 TB/s on
+// MI355X (complex128 accesses gain nothing and stay ordinary).
+typedef float f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f4v ld_nt(const void *p) { return __builtin_nontemporal_load((const f4v *)p); }
+__device__ __forceinline__ void st_nt(void *p, f4v v) { __builtin_nontemporal_store(v, (f4v *)p); }
+template <typename C, int VG, bool NT = true> __device__ __forceinline__ void ld_vg(const C *p, C (&out)[VG]) {
     if constexpr (VG == 2 && sizeof(C) == 8) {
-        const F4 q = *reinterpret_cast<const F4 *>(p);
-        out[0].x = q.a;
-        out[0].y = q.b;
-        out[1].x = q.c;
-        out[1].y = q.d;
+        const f4v q = NT ? ld_nt(p) : *reinterpret_cast<const f4v *>(p);
+        out[0].x = q.x;
+        out[0].y = q.y;
+        out[1].x = q.z;
+        out[1].y = q.w;
     } else {
 #pragma unroll
         for (int r = 0; r < VG; ++r) out[r] = p[r];
     }
 }
-template <typename C, int VG> __device__ __forceinline__ void st_vg(C *p, const C (&in)[VG]) {
+template <typename C, int VG, bool NT = true> __device__ __forceinline__ void st_vg(C *p, const C (&in)[VG]) {
     if constexpr (VG == 2 && sizeof(C) == 8) {
-        F4 q;
-        q.a = in[0].x;
-        q.b = in[0].y;
-        q.c = in[1].x;
-        q.d = in[1].y;
-        *reinterpret_cast<F4 *>(p) = q;
+        f4v q;
+        q.x = in[0].x;
+        q.y = in[0].y;
+        q.z = in[1].x;
+        q.w = in[1].y;
+        if constexpr (NT) st_nt(p, q);
+        else *reinterpret_cast<f4v *>(p) = q;
     } else {
 #pragma unroll
         for (int r = 0; r < VG; ++r) p[r] = in[r];
@@ -175,7 +181,7 @@ __global__ void __launch_bounds__(256) k_diag(C *__restrict__ psi, GroupArgs ga,
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int j = 0; j < M; ++j)
-                if (live[u]) ld_vg<C, VG>(psi + base[u] + da.offs[j], v[u][j]);
+                if (live[u]) ld_vg<C, VG, false>(psi + base[u] + da.offs[j], v[u][j]);
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -184,7 +190,7 @@ __global__ void __launch_bounds__(256) k_diag(C *__restrict__ psi, GroupArgs ga,
                 C o[VG];
 #pragma unroll
                 for (int r = 0; r < VG; ++r) o[r] = cmul(da.fac[j], v[u][j][r]);
-                st_vg<C, VG>(psi + base[u] + da.offs[j], o);
+                st_vg<C, VG, false>(psi + base[u] + da.offs[j], o);
             }
     }
 }
@@ -237,10 +243,10 @@ template <typename C> __device__ inline C shfl_xor_c(C v, int lanemask) {
     return r;
 }
 
-template <typename C, int VEC>
+template <typename C, int VEC, int U>
 __global__ void __launch_bounds__(256) k_low1(C *__restrict__ psi, Low1Args<C> a) {
     constexpr int LV = (VEC == 1) ? 0 : (VEC == 2) ? 1 : 2;
-    constexpr int U = 4;   // vectors per lane per iteration, all loaded before use
+    // U vectors per lane per iteration, all loaded before use
     const uint64_t span = (uint64_t)U * blockDim.x;
     // nvec is a multiple of 64 and a wave's 64 lanes hold 64 consecutive
     // aligned vectors, so they are all live or all idle for every u: the
@@ -250,9 +256,18 @@ __global__ void __launch_bounds__(256) k_low1(C *__restrict__ psi, Low1Args<C> a
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint64_t w = w0 + (uint64_t)u * blockDim.x;
-            if (w < a.nvec)
+            if (w < a.nvec) {
+                if constexpr (VEC == 2 && sizeof(C) == 8) {
+                    const f4v q = ld_nt(psi + w * VEC);
+                    v[u][0].x = q.x;
+                    v[u][0].y = q.y;
+                    v[u][1].x = q.z;
+                    v[u][1].y = q.w;
+                } else {
 #pragma unroll
-                for (int j = 0; j < VEC; ++j) v[u][j] = psi[w * VEC + j];
+                    for (int j = 0; j < VEC; ++j) v[u][j] = psi[w * VEC + j];
+                }
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -287,7 +302,61 @@ __global__ void __launch_bounds__(256) k_low1(C *__restrict__ psi, Low1Args<C> a
 #pragma unroll
             for (int j = 0; j < VEC; ++j) {
                 const bool on = ((i0 + j) & a.cmask) == a.cmask;
-                psi[i0 + j] = on ? o[j] : v[u][j];
+                o[j] = on ? o[j] : v[u][j];
+            }
+            if constexpr (VEC == 2 && sizeof(C) == 8) {
+                f4v q;
+                q.x = o[0].x;
+                q.y = o[0].y;
+                q.z = o[1].x;
+                q.w = o[1].y;
+                st_nt(psi + i0, q);
+            } else {
+#pragma unroll
+                for (int j = 0; j < VEC; ++j) psi[i0 + j] = o[j];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ scale
+//
+// psi <- s psi for a complex constant s: one 16-byte vector per thread in a
+// one-shot grid (two per thread beyond 2^32 threads), nontemporal for
+// complex64.  Besides normalisation and global phases, this is the plain
+// in-place stream every gate kernel is measured against.
+template <typename C, int U>
+__global__ void __launch_bounds__(256) k_scale(C *__restrict__ psi, uint64_t nvec, double sr, double si) {
+    const uint64_t span = (uint64_t)U * blockDim.x;
+    for (uint64_t w0 = (uint64_t)blockIdx.x * span + threadIdx.x; w0 < nvec; w0 += (uint64_t)gridDim.x * span) {
+        if constexpr (sizeof(C) == 8) {
+            f4v v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (w0 + u * blockDim.x < nvec) v[u] = ld_nt(psi + 2 * (w0 + u * blockDim.x));
+            const float r = (float)sr, i = (float)si;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (w0 + u * blockDim.x >= nvec) continue;
+                f4v o;
+                o.x = v[u].x * r - v[u].y * i;
+                o.y = v[u].x * i + v[u].y * r;
+                o.z = v[u].z * r - v[u].w * i;
+                o.w = v[u].z * i + v[u].w * r;
+                st_nt(psi + 2 * (w0 + u * blockDim.x), o);
+            }
+        } else {
+            C v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (w0 + u * blockDim.x < nvec) v[u] = psi[w0 + u * blockDim.x];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (w0 + u * blockDim.x >= nvec) continue;
+                C o;
+                o.x = v[u].x * sr - v[u].y * si;
+                o.y = v[u].x * si + v[u].y * sr;
+                psi[w0 + u * blockDim.x] = o;
             }
         }
     }
@@ -328,16 +397,10 @@ template <typename C> static C to_c(const double *z) {
     return r;
 }
 
-// Paired complex64 groups with 16-byte members stream best with one unit
-// per thread unless the members lie far apart (2^24 amplitudes or more),
-// where four units keep more loads in flight (30 qubits, one-qubit gate on
-// qubit 10: 5.28 -> 5.65 TB/s with one unit; on qubit 29: 5.44 with four,
-// 5.24 with one).
-static bool members_far(const GateAnalysis &a, int M) {
-    uint64_t top = 0;
-    for (int j = 0; j < M; ++j) top = std::max<uint64_t>(top, a.offs[j]);
-    return top >= (1ull << 24);
-}
+// Paired complex64 groups with 16-byte nontemporal members stream best with
+// one unit per thread wherever the members lie (30 qubits, one-qubit gate:
+// 6.1-6.6 TB/s for targets 12-20, 5.5 for 22-29 with one or two units; 33
+// qubits, target 32: 6.2 with one unit, 5.7 with two).
 
 template <typename C, int M>
 static void launch_dense_m(C *psi, const GateAnalysis &a, const GroupArgs &ga, const C *dmat, hipStream_t s) {
@@ -349,7 +412,7 @@ static void launch_dense_m(C *psi, const GateAnalysis &a, const GroupArgs &ga, c
     da.dmat = dmat;
     constexpr int UU = Unroll<C, M>::U;
     if (!vg2(ga)) hipLaunchKernelGGL((k_dense<C, M, 1, UU>), dim3(grid_for(ga.ngroups, 256 * UU)), dim3(256), 0, s, psi, ga, da);
-    else if (UU > 1 && !members_far(a, M))
+    else if (UU > 1)
         hipLaunchKernelGGL((k_dense<C, M, 2, 1>), dim3(grid_for(ga.ngroups / 2, 256)), dim3(256), 0, s, psi, ga, da);
     else hipLaunchKernelGGL((k_dense<C, M, 2, UU>), dim3(grid_for(ga.ngroups / 2, 256 * UU)), dim3(256), 0, s, psi, ga, da);
 }
@@ -382,7 +445,7 @@ static void launch_perm_m(C *psi, const GateAnalysis &a, const GroupArgs &ga, hi
     }
     constexpr int UU = Unroll<C, M>::U;
     if (!vg2(ga)) hipLaunchKernelGGL((k_perm<C, M, 1, UU>), dim3(grid_for(ga.ngroups, 256 * UU)), dim3(256), 0, s, psi, ga, pa);
-    else if (UU > 1 && !members_far(a, M))
+    else if (UU > 1)
         hipLaunchKernelGGL((k_perm<C, M, 2, 1>), dim3(grid_for(ga.ngroups / 2, 256)), dim3(256), 0, s, psi, ga, pa);
     else hipLaunchKernelGGL((k_perm<C, M, 2, UU>), dim3(grid_for(ga.ngroups / 2, 256 * UU)), dim3(256), 0, s, psi, ga, pa);
 }
@@ -405,7 +468,13 @@ static bool try_low1(C *psi, const GateAnalysis &a, hipStream_t s) {
     la.cmask = a.cmask;
     la.nvec = (1ull << a.n) / VEC;
     la.t = t;
-    hipLaunchKernelGGL((k_low1<C, VEC>), dim3(grid_for(la.nvec, 256 * 4)), dim3(256), 0, s, psi, la);
+    // one vector per lane in a one-shot grid (6.6 TB/s at 30 qubits against
+    // 5.4 with four per lane); two per lane once one each would exceed the
+    // 2^32 threads of a launch (33 qubits)
+    if (la.nvec / 256 <= 0xffffffffull / 256)
+        hipLaunchKernelGGL((k_low1<C, VEC, 1>), dim3(grid_for(la.nvec, 256)), dim3(256), 0, s, psi, la);
+    else
+        hipLaunchKernelGGL((k_low1<C, VEC, 2>), dim3(grid_for(la.nvec, 256 * 2)), dim3(256), 0, s, psi, la);
     return true;
 }
 
@@ -474,6 +543,21 @@ static int launch_gate_t(void *state, const GateAnalysis &a, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (dmat) staging_release(slot, s);
     if (e != hipSuccess) return hip_fail(e, "gate kernel launch");
+    return QSV_OK;
+}
+
+int launch_scale(void *state, int n, int dtype, double re, double im, hipStream_t s) {
+    // n >= 1: a complex64 state holds at least one 16-byte vector
+    const uint64_t nvec = dtype == QSV_C64 ? (1ull << n) / 2 : (1ull << n);
+    const bool one = nvec <= 0xffffffffull - 255;
+    if (dtype == QSV_C64) {
+        if (one) hipLaunchKernelGGL((k_scale<float2, 1>), dim3(grid_for(nvec, 256)), dim3(256), 0, s, (float2 *)state, nvec, re, im);
+        else hipLaunchKernelGGL((k_scale<float2, 2>), dim3(grid_for(nvec, 512)), dim3(256), 0, s, (float2 *)state, nvec, re, im);
+    } else {
+        if (one) hipLaunchKernelGGL((k_scale<double2, 1>), dim3(grid_for(nvec, 256)), dim3(256), 0, s, (double2 *)state, nvec, re, im);
+        else hipLaunchKernelGGL((k_scale<double2, 2>), dim3(grid_for(nvec, 512)), dim3(256), 0, s, (double2 *)state, nvec, re, im);
+    }
+    QSV_HIP_CHECK(hipGetLastError());
     return QSV_OK;
 }
 

@@ -139,7 +139,8 @@ class Gen {
   public:
     Gen(const PassProgram &p, int dtype, const JitVariant &v)
         : P(p), f32(dtype == QSV_C64), NR(1 << p.RB), pool_offset(((const PassHeaderDev *)p.blob.data())->off_pool),
-          share(v.share), PF(v.prefetch && pass_jit_prefetch(p, dtype)) {}
+          terms_offset(((const PassHeaderDev *)p.blob.data())->off_terms), share(v.share && !p.param),
+          PF(v.prefetch && pass_jit_prefetch(p, dtype)), param(p.param) {}
     std::string source();
 
   private:
@@ -147,11 +148,22 @@ class Gen {
     const bool f32;
     const int NR;
     const int pool_offset;   // byte offset of the real pool in the serialised program
+    const int terms_offset;  // byte offset of the phase terms in the serialised program
     std::string s;
     int uid = 0;
     double scale_re = 1.0, scale_im = 0.0;   // complex factor owed by every amplitude of the tile (see gate())
     const bool share;     // form products of phase factors shared by several amplitudes once
     const bool PF;        // prefetch the next chunk (persistent workgroups)
+    // Parametric kernel: matrix entries, phase angles and constant phase
+    // tables are read from the program at run time (uniform loads) instead
+    // of being compiled in, so the source depends only on the circuit's
+    // structure (which gates act on which bits) and a circuit whose angles
+    // change reuses the compiled kernel.  Nothing is specialised on values:
+    // no zero entries dropped, no factored skeletons, no free quarter turns.
+    const bool param;
+    // the angle of phase term k as the kernel reads it
+    std::string theta(int k) const { return param ? fmt("tth[%d]", 1 + 3 * k) : u64(P.terms[k].theta); }
+    void gate_param(const PassOpDev &op, const std::vector<int> &bits, bool real);
 
     void ln(const std::string &x) { s += x, s += '\n'; }
     double R(double v) const { v = snap(v); return f32 ? (double)(float)v : v; }   // value as the kernel's real type holds it
@@ -298,6 +310,57 @@ void Gen::gate(const PassOpDev &op, const std::vector<int> &bits, const std::vec
     ln("        }");
 }
 
+// One- or two-qubit gate with its matrix read from the pool (parametric
+// kernels): the same group structure as gate(), every entry a variable.
+void Gen::gate_param(const PassOpDev &op, const std::vector<int> &bits, bool real) {
+    const int k = (int)bits.size(), d = 1 << k;
+    const bool tok = op.ct != 0 || op.cn != 0;
+    const int id = uid++;
+    std::string dec = "        {";
+    for (int e = 0; e < d * d; ++e) {
+        if (real) dec += fmt(" const R m%d_%dr = pool[%d];", id, e, op.mat + e);
+        else dec += fmt(" const R m%d_%dr = pool[%d], m%d_%di = pool[%d];", id, e, op.mat + 2 * e, id, e, op.mat + 2 * e + 1);
+    }
+    ln(dec);
+    if (tok) ln(fmt("          const bool tk = ((t & %uu) == %uu) && ((base & %s) == %s);", op.ct, op.ct,
+                    u64(op.cn).c_str(), u64(op.cn).c_str()));
+    uint32_t gm = 0;
+    for (int b : bits) gm |= 1u << b;
+    for (int j = 0; j < NR; ++j) {
+        if (j & gm) continue;
+        if (((uint32_t)j & op.cj) != op.cj) continue;
+        std::vector<int> idx(d);
+        for (int r = 0; r < d; ++r) {
+            int x = j;
+            for (int q = 0; q < k; ++q)
+                if ((r >> (k - 1 - q)) & 1) x |= 1 << bits[q];
+            idx[r] = x;
+        }
+        std::string body = "            {";
+        for (int r = 0; r < d; ++r) body += fmt(" const C a%d = v[%d];", r, idx[r]);
+        ln(body);
+        for (int r = 0; r < d; ++r) {
+            std::string ex, ey;
+            for (int c = 0; c < d; ++c) {
+                const int e = r * d + c;
+                if (real) {
+                    ex += fmt("%sm%d_%dr * a%d.x", c ? " + " : "", id, e, c);
+                    ey += fmt("%sm%d_%dr * a%d.y", c ? " + " : "", id, e, c);
+                } else {
+                    ex += fmt("%sm%d_%dr * a%d.x - m%d_%di * a%d.y", c ? " + " : "", id, e, c, id, e, c);
+                    ey += fmt("%sm%d_%dr * a%d.y + m%d_%di * a%d.x", c ? " + " : "", id, e, c, id, e, c);
+                }
+            }
+            if (tok)
+                ln(fmt("              v[%d].x = tk ? (R)(%s) : a%d.x; v[%d].y = tk ? (R)(%s) : a%d.y;", idx[r],
+                       ex.c_str(), r, idx[r], ey.c_str(), r));
+            else ln(fmt("              v[%d].x = %s; v[%d].y = %s;", idx[r], ex.c_str(), idx[r], ey.c_str()));
+        }
+        ln("            }");
+    }
+    ln("        }");
+}
+
 // Phase factors of an op (see PassOpDev), applied to the register tile.
 void Gen::phase(const PassOpDev &op, int sk) {
     const int RB = P.RB;
@@ -314,9 +377,9 @@ void Gen::phase(const PassOpDev &op, int sk) {
             std::string e;
             for (int kI = sd.begin; kI < sd.end; ++kI) {
                 const PassTermDev &tm = P.terms[kI];
-                if (tm.mn == 0) e += fmt(" + %s", u64(tm.theta).c_str());
+                if (tm.mn == 0) e += fmt(" + %s", theta(kI).c_str());
                 else e += fmt(" + (((base & %s) == %s) ? %s : 0ull)", u64(tm.mn).c_str(), u64(tm.mn).c_str(),
-                              u64(tm.theta).c_str());
+                              theta(kI).c_str());
             }
             ln(fmt("          if (lane == %d) sph = 0ull%s;", sI - s0, e.c_str()));
         }
@@ -371,6 +434,26 @@ void Gen::phase(const PassOpDev &op, int sk) {
             cim = R(P.pool[op.fc + 2 * j + 1]);
         }
     };
+    if (param) {
+        // f_j = h_j * Fc[j] with Fc read from the pool; general terms as below
+        for (int j = 0; j < NR; ++j) {
+            if (sk >= 0 && ((j >> sk) & 1)) continue;
+            const int tj = sk >= 0 ? (j | (1 << sk)) : j;
+            if (!h_one[j]) ln(fmt("          v[%d] = cm(v[%d], %s);", tj, tj, h[j].c_str()));
+            if (op.fc >= 0)
+                ln(fmt("          v[%d] = cml(v[%d], pool[%d], pool[%d]);", tj, tj, op.fc + 2 * j, op.fc + 2 * j + 1));
+            std::string e;
+            for (int kI = op.gen_b; kI < op.gen_e; ++kI) {
+                const PassTermDev &tm = P.terms[kI];
+                if (((uint32_t)j & tm.mj) != tm.mj) continue;
+                e += fmt(" + ((((t & %uu) == %uu) && ((base & %s) == %s)) ? %s : 0ull)", tm.mt, tm.mt,
+                         u64(tm.mn).c_str(), u64(tm.mn).c_str(), theta(kI).c_str());
+            }
+            if (!e.empty()) ln(fmt("          v[%d] = cm(v[%d], expi(0ull%s));", tj, tj, e.c_str()));
+        }
+        ln("        }");
+        return;
+    }
     typedef std::pair<std::string, std::pair<double, double>> Key;
     std::map<Key, int> uses;
     for (int j = 0; j < NR; ++j) {
@@ -416,7 +499,7 @@ void Gen::phase(const PassOpDev &op, int sk) {
             const PassTermDev &tm = P.terms[kI];
             if (((uint32_t)j & tm.mj) != tm.mj) continue;
             e += fmt(" + ((((t & %uu) == %uu) && ((base & %s) == %s)) ? %s : 0ull)", tm.mt, tm.mt,
-                     u64(tm.mn).c_str(), u64(tm.mn).c_str(), u64(tm.theta).c_str());
+                     u64(tm.mn).c_str(), u64(tm.mn).c_str(), theta(kI).c_str());
         }
         if (!e.empty()) ln(fmt("          v[%d] = cm(v[%d], expi(0ull%s));", tj, tj, e.c_str()));
     }
@@ -450,8 +533,18 @@ std::string Gen::source() {
     ln("__device__ __forceinline__ unsigned long long sreg(unsigned long long x) {");
     ln("    return ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(x >> 32)) << 32) |");
     ln("           (unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)x); }");
-    ln("__device__ __forceinline__ C ldg(unsigned long long ub, unsigned off) { return *(const GLB C *)((const GLB char *)ub + off); }");
-    ln("__device__ __forceinline__ void stg(unsigned long long ub, unsigned off, C v) { *(GLB C *)((GLB char *)ub + off) = v; }");
+    if (f32) {
+        // complex64 amplitudes stream nontemporally: each is loaded and
+        // stored once per pass
+        ln("typedef float V2 __attribute__((ext_vector_type(2)));");
+        ln("__device__ __forceinline__ C ldg(unsigned long long ub, unsigned off) {");
+        ln("    const V2 v = __builtin_nontemporal_load((const GLB V2 *)((const GLB char *)ub + off)); C r; r.x = v.x; r.y = v.y; return r; }");
+        ln("__device__ __forceinline__ void stg(unsigned long long ub, unsigned off, C v) {");
+        ln("    V2 w; w.x = v.x; w.y = v.y; __builtin_nontemporal_store(w, (GLB V2 *)((GLB char *)ub + off)); }");
+    } else {
+        ln("__device__ __forceinline__ C ldg(unsigned long long ub, unsigned off) { return *(const GLB C *)((const GLB char *)ub + off); }");
+        ln("__device__ __forceinline__ void stg(unsigned long long ub, unsigned off, C v) { *(GLB C *)((GLB char *)ub + off) = v; }");
+    }
     if (f32) {
         ln("__device__ __forceinline__ C expi(unsigned long long ph) {");
         ln("    const float x = (float)(int)(unsigned)(ph >> 32) * 2.3283064365386963e-10f;");
@@ -485,6 +578,11 @@ std::string Gen::source() {
     if (any_exchange) ln(fmt("    __shared__ C lds[%d];", 1 << L));
     ln(fmt("    const R *pool = (const R *)(prog + %d);", pool_offset));
     ln("    (void)pool;");
+    if (param) {
+        // phase terms as 64-bit words (mn, theta, mt | mj << 32): theta of term k at word 1 + 3 k
+        ln(fmt("    const unsigned long long *tth = (const unsigned long long *)(prog + %d);", terms_offset));
+        ln("    (void)tth;");
+    }
     ln("    const unsigned t = threadIdx.x;");
     ln("    const int lane = (int)(t & 63u);");
     ln("    (void)lane;");
@@ -603,12 +701,14 @@ std::string Gen::source() {
             std::vector<double> M;
             const int cnt = op.kind == POP_G1 ? 8 : 4;
             for (int e = 0; e < cnt; ++e) M.push_back(P.pool[op.mat + e]);
-            gate(op, {op.a}, M, op.kind == POP_G1R);
+            if (param) gate_param(op, {op.a}, op.kind == POP_G1R);
+            else gate(op, {op.a}, M, op.kind == POP_G1R);
             break;
         }
         case POP_G2: {
             std::vector<double> M(P.pool.begin() + op.mat, P.pool.begin() + op.mat + 32);
-            gate(op, {op.a, op.b}, M, false);
+            if (param) gate_param(op, {op.a, op.b}, false);
+            else gate(op, {op.a, op.b}, M, false);
             break;
         }
         case POP_PHASE: phase(op, -1); break;
@@ -895,6 +995,7 @@ int jit_compile_plan(qsv_plan *p) {
     for (auto &op : p->ops)
         if (op.kind == PlanOp::PASS && !op.pass->jit) progs.push_back(op.pass.get());
     if (progs.empty()) return QSV_OK;
+    for (auto *pr : progs) pr->param = p->opts.jit == 2;
     std::vector<std::string> srcs(progs.size());
     std::vector<std::shared_ptr<JitModule>> mods(progs.size());
     std::vector<size_t> todo;

@@ -234,6 +234,7 @@ int qsv_plan_create(int n, int dtype, const qsv_gate *gates, int ngates, const q
     if (o.mode < 0 || o.mode > QSV_PLAN_LEARNED) return fail(QSV_ERR_ARG, "unknown plan mode");
     if (o.kmax == 0) o.kmax = 2;
     if (o.kmax < 1 || o.kmax > QSV_MAX_TARGETS) return fail(QSV_ERR_ARG, "kmax must be in [1, 6]");
+    if (o.jit < 0 || o.jit > 2) return fail(QSV_ERR_ARG, "jit must be 0, 1 or 2");
     int st = validate_common(n, dtype, nullptr, 0, nullptr, 0);
     if (st) return st;
     std::unique_ptr<qsv_plan> p(new qsv_plan());

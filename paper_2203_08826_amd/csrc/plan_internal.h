@@ -2,6 +2,7 @@
 // of a pass program).
 #pragma once
 
+#include <cstddef>
 #include <memory>
 #include <vector>
 
@@ -77,6 +78,9 @@ struct PassTermDev {
     uint32_t mj;
 };
 
+// parametric compiled kernels read theta as 64-bit word 1 + 3 k of the terms
+static_assert(sizeof(PassTermDev) == 24 && offsetof(PassTermDev, theta) == 8, "phase term layout");
+
 // A slot: the chunk-dependent phase sum of terms [begin, end), applied in
 // the threads whose index covers mt.
 struct PassSlotDev {
@@ -117,6 +121,7 @@ struct PassProgram {
     std::vector<uint8_t> blob;            // serialised program
     std::shared_ptr<JitModule> jit;       // compiled kernel, when the plan asked for one
     std::vector<int> pair_sigma;          // if set: chunk c is stored at chunk pair_sigma(c) (compiled kernel only)
+    bool param = false;                   // compiled kernel reads matrices and phases from the program
     void serialise();
 };
 

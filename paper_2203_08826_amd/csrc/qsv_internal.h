@@ -111,6 +111,7 @@ size_t staging_slot_bytes();
 // ---------------------------------------------------------------- launchers
 
 int launch_gate(void *state, int dtype, const GateAnalysis &a, hipStream_t s);
+int launch_scale(void *state, int n, int dtype, double re, double im, hipStream_t s);
 int launch_block_mfma(void *state, int n, const double *G, const int *targets, int k, hipStream_t s);
 int launch_block_valu(void *state, int n, int dtype, const double *G, const int *targets, int k, hipStream_t s);
 

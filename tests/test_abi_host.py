@@ -118,6 +118,29 @@ def test_pass_compilation_on_host():
     assert qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_PASSES).stats()["n_jit_passes"] == 0
 
 
+def test_parametric_passes_depend_only_on_structure():
+    """jit=2: matrices and angles are read from the program, so two circuits
+    that differ only in their angles compile to the same kernel sources, and
+    the second plan finds every kernel compiled already (re-binding the
+    angles of an ansatz costs host planning only)."""
+    import time
+    n = 14
+    a = qsv.qsv_plan_create(n, qsv.QSV_C64, W.variational(n, 3, seed=1), mode=qsv.PLAN_PASSES, jit=2)
+    t0 = time.perf_counter()
+    b = qsv.qsv_plan_create(n, qsv.QSV_C64, W.variational(n, 3, seed=2), mode=qsv.PLAN_PASSES, jit=2)
+    assert time.perf_counter() - t0 < 2.0   # a compilation takes seconds
+    na = a.stats()["n_launches"]
+    assert na == b.stats()["n_launches"] and a.stats()["n_jit_passes"] == na
+    sa = [qsv.qsv_plan_op_source(a, i) for i in range(na)]
+    assert sa == [qsv.qsv_plan_op_source(b, i) for i in range(na)]
+    # literal kernels (jit=1) differ with the angles
+    c = qsv.qsv_plan_create(n, qsv.QSV_C64, W.variational(n, 1, seed=1), mode=qsv.PLAN_PASSES, jit=1)
+    d = qsv.qsv_plan_create(n, qsv.QSV_C64, W.variational(n, 1, seed=2), mode=qsv.PLAN_PASSES, jit=1)
+    assert qsv.qsv_plan_op_source(c, 0) != qsv.qsv_plan_op_source(d, 0)
+    with pytest.raises(qsv.QsvError):
+        qsv.qsv_plan_create(n, qsv.QSV_C64, W.qft(n), mode=qsv.PLAN_PASSES, jit=3)
+
+
 def test_final_permutation_folds_only_when_it_saves_a_sweep():
     n = 20
     circ = [W.gate("H", [q]) for q in range(4)] + [W.gate("SWAP", [i, n - 1 - i]) for i in range(n // 2)]

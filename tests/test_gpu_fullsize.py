@@ -65,3 +65,107 @@ def test_supremacy30_passes_equal_per_gate(gpu):
     assert 1 - (ov[0] ** 2 + ov[1] ** 2) / (na * nb) <= 1e-6
     ys = torch.from_numpy(np.random.default_rng(1).integers(0, 1 << n, size=1 << 16)).cuda()
     assert torch.max(torch.abs(a[ys] - b[ys])).item() <= 1e-5
+
+
+# ------------------------------------------------------------ sampled groups at full size
+#
+# A gate (Eq. 1) acts on each group -- the 2^k amplitudes that differ only in
+# the target bits, with every control bit set -- independently.  At 30-32
+# qubits the oracle applies the gate to sampled groups: their amplitudes are
+# gathered before the launch and compared with the same groups after it.
+
+def _groups(n, targets, controls, count, rng):
+    """[count, 2^k] amplitude indices of random groups, member tau at column
+    tau (targets[0] = most significant bit of tau)."""
+    k = len(targets)
+    base = rng.integers(0, 1 << n, size=count, dtype=np.int64)
+    for q in targets:
+        base &= ~(1 << q)
+    for q in controls:
+        base |= 1 << q
+    tau = np.arange(1 << k, dtype=np.int64)
+    off = np.zeros(1 << k, dtype=np.int64)
+    for j, q in enumerate(targets):
+        off |= ((tau >> (k - 1 - j)) & 1) << q
+    return base[:, None] | off[None, :]
+
+
+def _oracle_groups(G, x):
+    """Eq. 1 on every group: the groups stacked as the high bits of a
+    (log2 count + k)-qubit state whose low k bits are the targets."""
+    cnt, d = x.shape
+    k = d.bit_length() - 1
+    flat = S.apply_matrix(x.reshape(-1), G, list(range(k - 1, -1, -1)))
+    return flat.reshape(cnt, d)
+
+
+def _block_bound(k, u):
+    """Worst-case 2-norm error of one k-qubit block applied in floating point
+    with unit roundoff u (complex products, or the real-GEMM form of the
+    matrix cores: 2m-term real dot products), relative to the group's norm:
+    (4 m sqrt(m) + sqrt(m) + 1) u."""
+    m = 2 ** k
+    return (4 * m * np.sqrt(m) + np.sqrt(m) + 1) * u
+
+
+def _check_groups(st, n, G, targets, controls, apply, rng, count=4096):
+    import torch
+    idx = _groups(n, targets, controls, count, rng)
+    di = torch.from_numpy(idx.reshape(-1)).cuda()
+    x = st[di].cpu().numpy().astype(np.complex128).reshape(idx.shape)
+    # a sample of amplitudes outside the groups (a control bit 0) stays put
+    if controls:
+        free = rng.integers(0, 1 << n, size=count, dtype=np.int64) & ~(1 << controls[0])
+        dfree = torch.from_numpy(free).cuda()
+        before = st[dfree].clone()
+    apply(st)
+    torch.cuda.synchronize()
+    y = st[di].cpu().numpy().astype(np.complex128).reshape(idx.shape)
+    want = _oracle_groups(np.asarray(G, dtype=np.complex128), x)
+    rel = np.linalg.norm(y - want, axis=1) / np.linalg.norm(x, axis=1)
+    u = 2.0 ** -24 if st.dtype == torch.complex64 else 2.0 ** -53
+    assert np.max(rel) <= _block_bound(len(targets), u), np.max(rel)
+    if controls:
+        assert torch.equal(st[dfree], before)
+    return float(np.max(rel))
+
+
+@pytest.mark.parametrize("n", [30, 32])
+@pytest.mark.parametrize("k", [4, 5, 6])
+def test_mfma_block_full_size_sampled_groups(gpu, n, k):
+    import torch
+    rng = np.random.default_rng(1000 + 10 * n + k)
+    g = torch.Generator(device="cuda").manual_seed(n + k)
+    st = torch.randn(1 << n, dtype=torch.complex64, device="cuda", generator=g)
+    for qs in (list(range(n - 1, n - 1 - k, -1)), list(range(k)), [int(q) for q in rng.permutation(n)[:k]]):
+        u = W.random_unitary(k, rng)
+        _check_groups(st, n, u, qs, [], lambda s: qsv.qsv_apply_block(s, u, qs), rng)
+    del st
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dt,n", [("c64", 30), ("c64", 33), ("c128", 30)])
+def test_gate_kernels_full_size_sampled_groups(gpu, dt, n):
+    """Dense, controlled and two-qubit gates on low, middle and high qubits,
+    with the launch shapes of full-size states (one unit per thread, the
+    shuffle path on low qubits, grid-stride rounds at 33 qubits)."""
+    import torch
+    rng = np.random.default_rng(2000 + n)
+    tdt = torch.complex64 if dt == "c64" else torch.complex128
+    g = torch.Generator(device="cuda").manual_seed(n)
+    st = torch.randn(1 << n, dtype=tdt, device="cuda", generator=g)
+    H = np.array([[1, 1], [1, -1]]) / np.sqrt(2)
+    cases = [(H, [0], []), (H, [3], []), (H, [12], []), (H, [n - 8], []), (H, [n - 1], []),
+             (W.random_unitary(1, rng), [n - 2], [5]),
+             (W.random_unitary(2, rng), [n - 1, 3], []),
+             (W.random_unitary(2, rng), [n - 3, n - 5], [0]),
+             (W.random_unitary(3, rng), [1, n - 1, 17], [])]
+    for G, tg, cs in cases:
+        _check_groups(st, n, G, tg, cs, lambda s: qsv.qsv_apply_matrix(s, G, tg, cs), rng)
+    # fSim through its own entry point
+    th, ph = 0.7, 1.9
+    F = np.array([[1, 0, 0, 0], [0, np.cos(th), -1j * np.sin(th), 0], [0, -1j * np.sin(th), np.cos(th), 0],
+                  [0, 0, 0, np.exp(-1j * ph)]])
+    _check_groups(st, n, F, [n - 1, 10], [], lambda s: qsv.qsv_apply_fsim(s, n - 1, 10, th, ph), rng)
+    del st
+    torch.cuda.empty_cache()

@@ -226,3 +226,22 @@ def test_jit_deep_supremacy_with_lookahead(gpu, dt):
         assert sum(circ[i]["name"] != "CZ" for i in ids) <= 64
         order += ids
     assert sorted(order) == list(range(len(circ))) and order != sorted(order)
+
+
+@pytest.mark.parametrize("dt", [qsv.QSV_C64, qsv.QSV_C128])
+@pytest.mark.parametrize("name", sorted(CIRCUITS))
+@pytest.mark.parametrize("n", [12, 16])
+def test_parametric_passes_match_oracle(gpu, dt, name, n):
+    """jit=2 reads matrices and angles from the program at run time: same
+    results as the oracle; a second circuit of the same structure with other
+    angles reuses the kernels and is right too."""
+    circ = CIRCUITS[name](n)
+    psi0 = W.random_state(n, 8)
+    got, stats = _run(psi0, circ, dt, mode=qsv.PLAN_PASSES, jit=2)
+    if stats["n_passes"]:
+        assert stats["n_jit_passes"] >= 1, stats
+    assert np.max(np.abs(got - S.run_circuit(psi0, circ))) <= TOL[dt], (name, n, stats)
+    if name == "variational":
+        circ2 = W.variational(n, 3, seed=n + 100)
+        got2, _ = _run(psi0, circ2, dt, mode=qsv.PLAN_PASSES, jit=2)
+        assert np.max(np.abs(got2 - S.run_circuit(psi0, circ2))) <= TOL[dt]
