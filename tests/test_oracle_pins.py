@@ -335,3 +335,31 @@ def test_adam_first_step_closed_form():
     g = np.array([0.3, -2.0, 1e-3])
     p, m, v = M.adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr=0.01)
     assert np.allclose(p, -0.01 * g / (np.abs(g) + 1e-8), atol=1e-15)
+
+
+def test_golden_adjoint24_routes_agree():
+    """The stored 24-qubit gradients (tests/golden/adjoint24_cfg4.txt, written
+    by the oracle): on the seeded subset the oracle's adjoint equals its
+    parameter shift (exact for rotation gates, Sec. 3.4) to rounding, and
+    central finite differences with step 1e-5 agree to O(h^2); every one of
+    the 576 angles has an entry and the energy lies in [-E_max, E_max]."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "adjoint24_cfg4.txt")
+    energy, adj, sub = None, {}, {}
+    for line in open(path):
+        if line.startswith("# energy"):
+            energy = float(line.split()[2])
+        elif line.startswith("adjoint "):
+            _, i, g = line.split()
+            adj[int(i)] = float(g)
+        elif line.startswith("subset "):
+            _, i, ps, fd = line.split()
+            sub[int(i)] = (float(ps), float(fd))
+    assert sorted(adj) == list(range(576)) and len(sub) == 32
+    # |<H>| <= 23 bonds + 0.5 * 24 fields
+    assert energy is not None and abs(energy) <= 23 + 12
+    idx = sorted(sub)
+    a = np.array([adj[i] for i in idx])
+    ps = np.array([sub[i][0] for i in idx])
+    fd = np.array([sub[i][1] for i in idx])
+    assert np.max(np.abs(a - ps)) <= 1e-12
+    assert np.max(np.abs(fd - ps)) <= 1e-8
