@@ -3,7 +3,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqsv.so")
+# QSV_LIBRARY names another build of the same library (the sanitizer build
+# of the host code that the CPU tests load); by default the in-tree one.
+LIB_PATH = os.environ.get("QSV_LIBRARY") or os.path.join(HERE, "libqsv.so")
 
 QSV_OK = 0
 QSV_C64, QSV_C128 = 0, 1
@@ -79,6 +81,7 @@ SIGNATURES = {
     "qsv_plan_op_gates": ([_vp, _i, _vp, ctypes.c_size_t, _vp], _i),
     "qsv_apply_block": ([_vp, _i, _i, _vp, _vp, _i, _vp], _i),
     "qsv_run_pass": ([_vp, _i, _i, _vp, _i, _vp, _i, _vp], _i),
+    "qsv_sliced_run": ([_vp, _i, _i, _vp, _i, _i, _i, _i, _vp], _i),
     "qsv_probabilities": ([_vp, _i, _i, _vp, _i, _vp, _vp], _i),
     "qsv_probabilities_noalloc": ([_vp, _i, _i, _vp, _i, _vp, _vp], _i),
     "qsv_norm2": ([_vp, _i, _i, _vp, _vp], _i),

@@ -61,5 +61,46 @@ def build(verbose=True):
     return LIB
 
 
+SAN = os.path.join(BUILD, "san")
+SAN_LIB = os.path.join(SAN, "libqsv_san.so")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer"]
+
+
+def build_sanitized(verbose=True):
+    """A build whose host C++ (validation, planning, pass compilation,
+    bindings) runs under AddressSanitizer and UndefinedBehaviorSanitizer:
+    the host sources are compiled by g++ with the sanitizers and linked with
+    the unsanitized objects of the device sources from build().  Loaded with
+    the sanitizer runtime preloaded (LD_PRELOAD of g++'s libasan) and
+    QSV_LIBRARY pointing at it; returns the library path."""
+    hip_objs = sorted(glob.glob(os.path.join(BUILD, "*.hip.o")))
+    if len(hip_objs) != len(glob.glob(os.path.join(CSRC, "*.hip"))):
+        build(verbose)
+        hip_objs = sorted(glob.glob(os.path.join(BUILD, "*.hip.o")))
+    os.makedirs(SAN, exist_ok=True)
+    gxx = os.environ.get("CXX", "g++")
+    inc = ["-I" + os.path.join(HERE, "..", "include"), "-I/opt/rocm/include", "-D__HIP_PLATFORM_AMD__"]
+
+    def one(src):
+        obj = os.path.join(SAN, os.path.basename(src) + ".o")
+        cmd = [gxx, "-std=c++17", "-O1", "-g", "-fPIC"] + SAN_FLAGS + inc + ["-c", src, "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("g++ failed on %s:\n%s" % (src, r.stdout + r.stderr))
+        return obj
+
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.cpp")))
+    with cf.ThreadPoolExecutor(max_workers=min(len(srcs), int(os.environ.get("MAX_JOBS", "8")))) as ex:
+        objs = list(ex.map(one, srcs))
+    cmd = [gxx, "-shared"] + SAN_FLAGS + ["-o", SAN_LIB] + objs + hip_objs + [
+        "-L/opt/rocm/lib", "-lamdhip64", "-lhiprtc", "-Wl,-rpath,/opt/rocm/lib"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("sanitized link failed:\n" + r.stdout + r.stderr)
+    if verbose:
+        print("built", SAN_LIB)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
     build()

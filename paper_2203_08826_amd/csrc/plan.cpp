@@ -335,7 +335,8 @@ int qsv_plan_op_program(const qsv_plan *plan, int index, void *buf, size_t cap, 
     if (op.kind != PlanOp::PASS) return fail(QSV_ERR_ARG, "op is not an LDS pass");
     std::vector<uint8_t> blob = op.pass->blob;
     const PassHeaderDev *h = (const PassHeaderDev *)blob.data();
-    std::memcpy(blob.data() + h->off_pool, op.pass->pool.data(), op.pass->pool.size() * sizeof(double));
+    if (!op.pass->pool.empty())   // an empty vector's data() may be null, which memcpy does not allow
+        std::memcpy(blob.data() + h->off_pool, op.pass->pool.data(), op.pass->pool.size() * sizeof(double));
     *size = blob.size();
     if (buf) {
         if (cap < blob.size()) return fail(QSV_ERR_ARG, "buffer too small");
