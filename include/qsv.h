@@ -75,6 +75,19 @@ const char *qsv_status_string(int status);
 /* Message of the last failing call on this thread ("" if none). */
 const char *qsv_last_error(void);
 
+/* Device memory the library holds for itself, in bytes, summed over devices
+ * (the paper's memory comparison, Sec. 3.1, is of peak device memory per
+ * simulator; every gate, plan and reduction here works in place, so the
+ * caller's state plus this is the footprint).  Counted: the staging ring
+ * (256 slots of 256 KiB per device, allocated at first use, kept until the
+ * process ends) and per-call temporaries (adjoint partial sums, cost-model
+ * batches, the two slice buffers of qsv_sliced_run).  Not counted: code
+ * objects of compiled passes and the fixed scratch array of
+ * qsv_probabilities_noalloc.  `peak_bytes` is the largest total since the
+ * last reset; reset_peak != 0 sets it to the current total after reading.
+ * Either pointer may be NULL.  Host only; returns QSV_OK. */
+int qsv_memory_stats(uint64_t *current_bytes, uint64_t *peak_bytes, int reset_peak);
+
 /* Host-only validation of a gate's qubits (no HIP call; usable without a
  * GPU): 1 <= n <= QSV_MAX_QUBITS, dtype valid, 0 <= k <= QSV_MAX_TARGETS,
  * 0 <= c <= QSV_MAX_CONTROLS, k + c <= n, every index in [0, n), no repeats. */
@@ -254,6 +267,26 @@ int qsv_apply_block(void *state, int n, int dtype, const void *gate, const int *
  * be anywhere; SWAPs of two local qubits are permutations of the chunk. */
 int qsv_run_pass(void *state, int n, int dtype, const qsv_gate *gates, int ngates,
                  const int *local_qubits, int nlocal, void *stream);
+
+/* ------------------------------------------------------------------ states larger than device memory
+ * The paper's multi-device scheme on one re-used GPU: the state stays in host
+ * memory (2^n amplitudes of the dtype; pinned memory lets the copies overlap
+ * the kernels) and slices of 2^local_qubits amplitudes visit the device.  The
+ * qubits at or above local_qubits are global.  The circuit is cut into
+ * phases in which every non-diagonal target is local or one of at most
+ * active_qubits global qubits; each phase runs group by group, a group being
+ * the 2^(active) slices that differ only in the phase's active qubits, copied
+ * into a device buffer where controls and diagonal gates on the other global
+ * qubits are resolved from the group's values.  Each group runs a plan of
+ * `mode` QSV_PLAN_PER_GATE or QSV_PLAN_PASSES over local_qubits + active
+ * qubits.  The library allocates two device buffers of
+ * 2^(local_qubits + active_qubits) amplitudes and two copy streams for the
+ * call and frees them before returning; the call returns when the host state
+ * holds the result (kernels run on `stream`).  Errors: a gate with more
+ * global non-diagonal targets than active_qubits is QSV_ERR_ARG;
+ * 1 <= local_qubits <= n, 0 <= active_qubits <= min(8, n - local_qubits). */
+int qsv_sliced_run(void *host_state, int n, int dtype, const qsv_gate *gates, int ngates, int local_qubits,
+                   int active_qubits, int mode, void *stream);
 
 /* ------------------------------------------------------------------ reductions
  * Products are formed in the state's precision and accumulated in float64

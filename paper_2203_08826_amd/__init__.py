@@ -92,6 +92,13 @@ def qsv_last_error():
     return load().qsv_last_error().decode(errors="replace")
 
 
+def qsv_memory_stats(reset_peak=False):
+    """(current, peak) bytes of device memory the library holds for itself."""
+    cur, peak = ctypes.c_uint64(), ctypes.c_uint64()
+    check("qsv_memory_stats", load().qsv_memory_stats(ctypes.byref(cur), ctypes.byref(peak), int(bool(reset_peak))))
+    return cur.value, peak.value
+
+
 def qsv_validate(n, dtype, targets, controls=()):
     """Host-only validation; returns the status code (no exception)."""
     t, k = _ints(targets)
@@ -383,6 +390,29 @@ def qsv_apply_tfim(state, out, J=1.0, h=0.5, periodic=False, stream=None):
     check("qsv_apply_tfim", load().qsv_apply_tfim(p, po, n, dt, float(J), float(h), int(bool(periodic)),
                                                   _stream(stream)))
     return out
+
+
+# ------------------------------------------------------------------ host-resident states
+
+def qsv_sliced_run(host_state, circuit, local_qubits, active_qubits=2, mode=PLAN_PASSES, stream=None):
+    """Run `circuit` on a state in host memory (a contiguous CPU tensor,
+    complex64 or complex128, pinned for overlapped copies), slices of
+    2^local_qubits amplitudes visiting the device; returns when the host
+    state holds the result."""
+    torch = _torch()
+    t = host_state
+    if t.is_cuda or not t.is_contiguous():
+        raise ValueError("host_state must be a contiguous host tensor")
+    size = t.numel()
+    n = size.bit_length() - 1
+    if size < 2 or size != 1 << n:
+        raise ValueError("state length must be a power of two >= 2")
+    dt = _dtype_code(t)
+    arr, keep = gates_to_c(circuit)
+    check("qsv_sliced_run", load().qsv_sliced_run(ctypes.c_void_p(t.data_ptr()), n, dt, arr, len(circuit),
+                                                  int(local_qubits), int(active_qubits), int(mode), _stream(stream)))
+    del keep
+    return t
 
 
 # ------------------------------------------------------------------ measurement

@@ -102,6 +102,7 @@ SIGNATURES = {
     "qsv_mlp_param_count": ([_vp, _i], _i),
     "qsv_cost_model_set": ([_vp, _vp, _i, _vp, _vp], _i),
     "qsv_plan_op_features": ([_vp, _i, _vp], _i),
+    "qsv_memory_stats": ([_vp, _vp, _i], _i),
 }
 
 _lib = None

@@ -115,7 +115,7 @@ static int adjoint_t(void *psi, void *lam, int n, int dtype, const qsv_gate *gat
     int nblocks = (int)std::min<uint64_t>((max_groups + AT - 1) / AT, (uint64_t)device_sm_count() * 4);
     if (nblocks < 1) nblocks = 1;
     double *part = nullptr;
-    if (nparams > 0) QSV_HIP_CHECK(hipMallocAsync((void **)&part, sizeof(double) * (size_t)nparams * nblocks, s));
+    if (nparams > 0) QSV_HIP_CHECK(dev_malloc_async((void **)&part, sizeof(double) * (size_t)nparams * nblocks, s));
     int slot = nparams;
     int st = QSV_OK;
     for (int i = ngates - 1; i >= 0 && st == QSV_OK; --i) {
@@ -155,7 +155,7 @@ static int adjoint_t(void *psi, void *lam, int n, int dtype, const qsv_gate *gat
         if (e != hipSuccess) st = hip_fail(e, "adjoint finish launch");
     }
     if (part) {
-        hipError_t e = hipFreeAsync(part, s);
+        hipError_t e = dev_free_async(part, s);
         if (st == QSV_OK && e != hipSuccess) st = hip_fail(e, "hipFreeAsync");
     }
     return st;

@@ -260,6 +260,47 @@ GateAnalysis analyse_gate(int n, const double *G, const int *targets, int k, con
 // ---------------------------------------------------------------- staging ring
 
 namespace {
+std::mutex g_mem_mu;
+std::vector<std::pair<void *, size_t>> g_mem_live;   // few live allocations at any time
+uint64_t g_mem_cur = 0, g_mem_peak = 0;
+void mem_add(void *p, size_t bytes) {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    g_mem_live.emplace_back(p, bytes);
+    g_mem_cur += bytes;
+    g_mem_peak = std::max(g_mem_peak, g_mem_cur);
+}
+void mem_remove(void *p) {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    for (size_t i = 0; i < g_mem_live.size(); ++i)
+        if (g_mem_live[i].first == p) {
+            g_mem_cur -= g_mem_live[i].second;
+            g_mem_live[i] = g_mem_live.back();
+            g_mem_live.pop_back();
+            return;
+        }
+}
+}  // namespace
+
+hipError_t dev_malloc(void **p, size_t bytes) {
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) mem_add(*p, bytes);
+    return e;
+}
+hipError_t dev_malloc_async(void **p, size_t bytes, hipStream_t s) {
+    const hipError_t e = hipMallocAsync(p, bytes, s);
+    if (e == hipSuccess) mem_add(*p, bytes);
+    return e;
+}
+hipError_t dev_free(void *p) {
+    mem_remove(p);
+    return hipFree(p);
+}
+hipError_t dev_free_async(void *p, hipStream_t s) {
+    mem_remove(p);
+    return hipFreeAsync(p, s);
+}
+
+namespace {
 constexpr int kSlots = 256;
 constexpr size_t kSlotBytes = 256 << 10;
 constexpr int kMaxStagingSlots = 8;   // the largest request: 2 MiB in consecutive slots
@@ -288,7 +329,7 @@ int staging_acquire(size_t bytes, StagingSlot *slot) {
     DeviceStaging &st = g_staging[dev];
     if (!st.ready) {
         QSV_HIP_CHECK(hipHostMalloc((void **)&st.host, kSlots * kSlotBytes, hipHostMallocDefault));
-        QSV_HIP_CHECK(hipMalloc((void **)&st.dev, kSlots * kSlotBytes));
+        QSV_HIP_CHECK(dev_malloc((void **)&st.dev, kSlots * kSlotBytes));
         for (int i = 0; i < kSlots; ++i) {
             QSV_HIP_CHECK(hipEventCreateWithFlags(&st.ev[i], hipEventDisableTiming));
             st.armed[i] = false;
@@ -335,6 +376,14 @@ using namespace qsv;
 // ================================================================== C ABI
 
 extern "C" {
+
+int qsv_memory_stats(uint64_t *current_bytes, uint64_t *peak_bytes, int reset_peak) {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    if (current_bytes) *current_bytes = g_mem_cur;
+    if (peak_bytes) *peak_bytes = g_mem_peak;
+    if (reset_peak) g_mem_peak = g_mem_cur;
+    return QSV_OK;
+}
 
 int qsv_abi_version(void) { return QSV_ABI_VERSION; }
 

@@ -92,15 +92,15 @@ static int predict(const CostModel &m, const std::vector<const qsv_plan *> &cand
     for (int l = 1; l <= nl; ++l) acts += (size_t)B * m.sizes[l];
     float *dp = nullptr, *dx = nullptr, *da = nullptr, *dpred = nullptr;
     auto cleanup = [&]() {
-        if (dp) (void)hipFree(dp);
-        if (dx) (void)hipFree(dx);
-        if (da) (void)hipFree(da);
-        if (dpred) (void)hipFree(dpred);
+        if (dp) (void)dev_free(dp);
+        if (dx) (void)dev_free(dx);
+        if (da) (void)dev_free(da);
+        if (dpred) (void)dev_free(dpred);
     };
-    hipError_t e = hipMalloc((void **)&dp, sizeof(float) * m.params.size());
-    if (e == hipSuccess) e = hipMalloc((void **)&dx, sizeof(float) * X.size());
-    if (e == hipSuccess) e = hipMalloc((void **)&da, sizeof(float) * acts);
-    if (e == hipSuccess) e = hipMalloc((void **)&dpred, sizeof(float) * B);
+    hipError_t e = dev_malloc((void **)&dp, sizeof(float) * m.params.size());
+    if (e == hipSuccess) e = dev_malloc((void **)&dx, sizeof(float) * X.size());
+    if (e == hipSuccess) e = dev_malloc((void **)&da, sizeof(float) * acts);
+    if (e == hipSuccess) e = dev_malloc((void **)&dpred, sizeof(float) * B);
     if (e == hipSuccess) e = hipMemcpy(dp, m.params.data(), sizeof(float) * m.params.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dx, X.data(), sizeof(float) * X.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {

@@ -20,6 +20,14 @@ void clear_error();
 int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *where);
 
+// Device memory the library allocates for itself (the staging ring and
+// per-call temporaries) goes through these, which keep the current and peak
+// byte counts that qsv_memory_stats reports.
+hipError_t dev_malloc(void **p, size_t bytes);
+hipError_t dev_malloc_async(void **p, size_t bytes, hipStream_t s);
+hipError_t dev_free(void *p);
+hipError_t dev_free_async(void *p, hipStream_t s);
+
 #define QSV_HIP_CHECK(expr)                                   \
     do {                                                      \
         hipError_t e_ = (expr);                               \

@@ -260,3 +260,13 @@ def test_op_gates_of_per_gate_and_greedy_plans():
     blocks = qsv.qsv_plan_blocks(g)
     for b, members in enumerate(ops):
         assert all(blocks[i] == b for i in members)
+
+
+def test_memory_stats_on_the_host():
+    """qsv_memory_stats is host-only: the peak never falls below the
+    current total, and a reset brings the peak down to it."""
+    cur, peak = qsv.qsv_memory_stats()
+    assert peak >= cur >= 0
+    cur2, peak2 = qsv.qsv_memory_stats(reset_peak=True)
+    assert cur2 == cur
+    assert qsv.qsv_memory_stats() == (cur, cur)
