@@ -108,6 +108,14 @@ def workload_supremacy(args):
     print(json.dumps(out), flush=True)
 
 
+_T0 = time.perf_counter()
+
+
+def _progress(msg):
+    """A progress line on stderr (long workloads print one per stage)."""
+    print("[%7.1f s] %s" % (time.perf_counter() - _T0, msg), file=sys.stderr, flush=True)
+
+
 def workload_variational(args):
     """Variational ansatz fused into dense 5-qubit blocks on FP32 MFMA (c64),
     against the c128 reference (LDS passes, oracle-checked at small n)."""
@@ -116,6 +124,7 @@ def workload_variational(args):
     import workloads as W
     n = args.n
     circ = W.variational(n, args.layers, seed=0)
+    _progress("variational n=%d layers=%d: planning greedy kmax=5" % (n, args.layers))
     fused = qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_GREEDY, kmax=5, use_mfma=1)
     fs = fused.stats()
     a = _zero_state(n, torch.complex64)
@@ -124,6 +133,7 @@ def workload_variational(args):
     t_fused = _timed(lambda: qsv.qsv_plan_execute(fused, a), 1)
     a = _zero_state(n, torch.complex64)
     qsv.qsv_plan_execute(fused, a)
+    _progress("fused c64 %.4f s; c128 reference" % t_fused)
     ref_plan = qsv.qsv_plan_create(n, qsv.QSV_C128, circ, mode=qsv.PLAN_PASSES)
     b = _zero_state(n, torch.complex128)
     t0 = time.perf_counter()
@@ -133,6 +143,7 @@ def workload_variational(args):
     infid = _infidelity(qsv, b, a)
     # the same circuit as compiled LDS passes (c64), parametric kernels: a
     # second circuit of the same ansatz with new angles reuses them
+    _progress("reference %.3f s; compiling parametric passes" % t_ref)
     t0 = time.perf_counter()
     cp = qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_PASSES, jit=2)
     t_cp_create = time.perf_counter() - t0
@@ -215,14 +226,9 @@ def workload_learned(args):
         cost_model.load_into_library(args.model)
     n = args.n
     res = {}
-    rng = np.random.default_rng(3)
-    blocks = []
-    for _ in range(24):   # a family of dense 5- and 6-qubit unitaries on random qubits
-        k = int(rng.integers(5, 7))
-        g = W.gate("UNITARY", [int(q) for q in rng.choice(n, size=k, replace=False)])
-        g["matrix"] = W.random_unitary(k, rng)
-        blocks.append(g)
-    for name, circ in (("qft", W.qft(n)), ("supremacy_d30", W.supremacy(n, 30, seed=1)), ("dense_blocks", blocks)):
+    # dense 3-qubit unitaries in 5-qubit windows: fusing pays, passes cannot take them
+    windows = W.dense_windows(n, seed=3)
+    for name, circ in (("qft", W.qft(n)), ("supremacy_d30", W.supremacy(n, 30, seed=1)), ("dense_windows", windows)):
         row = {}
         states = {}
         for pname, kw in (("learned", dict(mode=qsv.PLAN_LEARNED, kmax=2, jit=args.jit)),
@@ -252,16 +258,41 @@ def workload_learned(args):
         torch.cuda.empty_cache()
         res[name] = row
     print(json.dumps({"metric": "measured s: learned vs greedy vs unfused", "config": {
-        "workload": "QFT, supremacy-like depth 30 and 24 dense 5-6 qubit unitaries at n=%d, complex64" % n,
+        "workload": "QFT, supremacy-like depth 30 and 32 dense 3-qubit unitaries in four 5-qubit windows at n=%d, complex64" % n,
         "model_loaded": loaded}, "results": res}),
         flush=True)
+
+
+def _touched_fraction(bits, pred, line_bits=0):
+    """Fraction of the state a gate reads and writes: of its amplitudes
+    (line_bits = 0), or of its 128-byte lines (line_bits = log2 of the
+    amplitudes per line), when it changes exactly the amplitudes whose values
+    of `bits` satisfy `pred`."""
+    import itertools
+    inside = [i for i, b in enumerate(bits) if b < line_bits]
+    hit = 0
+    outs = list(itertools.product([0, 1], repeat=len(bits) - len(inside)))
+    for o in outs:
+        if line_bits:   # a line counts when any of its amplitudes is touched
+            ok = False
+            for v_in in itertools.product([0, 1], repeat=len(inside)):
+                v, it_in, it_out = [], iter(v_in), iter(o)
+                for i in range(len(bits)):
+                    v.append(next(it_in) if i in inside else next(it_out))
+                ok = ok or bool(pred(v))
+            hit += ok
+        else:
+            hit += bool(pred(list(o)))
+    return hit / len(outs)
 
 
 def workload_single_gate(args):
     """Per-gate kernels on their own: dense one-qubit gates on a low, middle
     and high qubit, X, Z, a controlled phase, SWAP and fSim, each timed with
     HIP events on the launch stream over --steps launches, GB/s of touched
-    bytes (read + write of the amplitudes the gate changes)."""
+    bytes (read + write of the amplitudes the gate changes) and of the
+    128-byte lines holding them (complex64 lines hold 16 amplitudes, so a
+    gate with a bit below 4 changes part of every line it touches)."""
     import numpy as np
     import torch
     import paper_2203_08826_amd as qsv
@@ -273,17 +304,20 @@ def workload_single_gate(args):
         st = torch.zeros(1 << n, dtype=tdt, device="cuda")
         st[0] = 1.0
         full = 2.0 * (1 << n) * s
-        cases = (("H_q0", lambda: qsv.qsv_apply_matrix(st, H, [0]), full),
-                 ("H_q3", lambda: qsv.qsv_apply_matrix(st, H, [3]), full),
-                 ("H_q12", lambda: qsv.qsv_apply_matrix(st, H, [12]), full),
-                 ("H_q%d" % (n - 8), lambda: qsv.qsv_apply_matrix(st, H, [n - 8]), full),
-                 ("H_q%d" % (n - 1), lambda: qsv.qsv_apply_matrix(st, H, [n - 1]), full),
-                 ("X_q%d" % (n - 1), lambda: qsv.qsv_apply_x(st, n - 1), full),
-                 ("Z_q5", lambda: qsv.qsv_apply_z(st, 5), full / 2),
-                 ("CU1_c3_t20", lambda: qsv.qsv_apply_phase(st, 20, 0.3, [3]), full / 4),
-                 ("SWAP_3_20", lambda: qsv.qsv_apply_swap(st, 3, 20), full / 2),
-                 ("fSim_10_20", lambda: qsv.qsv_apply_fsim(st, 10, 20, 0.4, 0.7), full * 0.75))
-        for name, fn, nbytes in cases:
+        every = ([], lambda v: True)
+        cases = (("H_q0", lambda: qsv.qsv_apply_matrix(st, H, [0]), every),
+                 ("H_q3", lambda: qsv.qsv_apply_matrix(st, H, [3]), every),
+                 ("H_q12", lambda: qsv.qsv_apply_matrix(st, H, [12]), every),
+                 ("H_q%d" % (n - 8), lambda: qsv.qsv_apply_matrix(st, H, [n - 8]), every),
+                 ("H_q%d" % (n - 1), lambda: qsv.qsv_apply_matrix(st, H, [n - 1]), every),
+                 ("X_q%d" % (n - 1), lambda: qsv.qsv_apply_x(st, n - 1), every),
+                 ("Z_q5", lambda: qsv.qsv_apply_z(st, 5), ([5], lambda v: v[0])),
+                 ("CU1_c3_t20", lambda: qsv.qsv_apply_phase(st, 20, 0.3, [3]), ([3, 20], lambda v: v[0] and v[1])),
+                 ("SWAP_3_20", lambda: qsv.qsv_apply_swap(st, 3, 20), ([3, 20], lambda v: v[0] != v[1])),
+                 ("fSim_10_20", lambda: qsv.qsv_apply_fsim(st, 10, 20, 0.4, 0.7), ([10, 20], lambda v: v[0] or v[1])))
+        for name, fn, touched in cases:
+            nbytes = full * _touched_fraction(*touched)
+            lbytes = full * _touched_fraction(*touched, line_bits=(128 // s).bit_length() - 1)
             fn()
             torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
@@ -295,7 +329,8 @@ def workload_single_gate(args):
             e1.synchronize()
             sec = e0.elapsed_time(e1) / 1e3 / args.steps
             res["%s_%s" % (name, dname)] = {"ms": round(sec * 1e3, 3), "GB/s": round(nbytes / sec / 1e9, 1),
-                                            "frac": round(nbytes / sec / 1e9 / HBM_PEAK_GBS, 4)}
+                                            "frac": round(nbytes / sec / 1e9 / HBM_PEAK_GBS, 4),
+                                            "line_GB/s": round(lbytes / sec / 1e9, 1)}
             print("single_gate %s %s %.3f ms %.1f GB/s" % (dname, name, sec * 1e3, nbytes / sec / 1e9), flush=True)
         del st
         torch.cuda.empty_cache()

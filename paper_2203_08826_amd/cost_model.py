@@ -3,9 +3,13 @@
 Timings are recorded by the simulator itself: candidate plans (per-gate,
 greedy fusion kmax 2..5, LDS passes) are built for synthetic circuits and
 every op is timed alone with HIP events; each sample is the op's feature
-vector (``qsv_plan_op_features``) and the log of its median run time.  The
-MLP (12 -> 64 -> 64 -> 1, ReLU) is trained on the GPU with the library's
-own forward / backward / Adam kernels.  ``load_into_library`` hands the
+vector (``qsv_plan_op_features``) and the log of its median run time.  Two
+sources of samples: random fused blocks (Haar-random k-qubit unitaries,
+k = 2..6, on 26..33 qubits, targets low, high or mixed), each timed as a
+dense VALU gate and, for k >= 4, as a matrix-core block; and the ops of the
+candidate plans of synthetic circuits (QFT, supremacy-like, variational,
+random).  The MLP (13 -> 64 -> 64 -> 1, ReLU) is trained on the GPU with the
+library's own forward / backward / Adam kernels.  ``load_into_library`` hands the
 weights to ``qsv_cost_model_set`` so that ``PLAN_LEARNED`` can score plans.
 
 Usage (on a GPU):  python -m paper_2203_08826_amd.cost_model --out model.npz
@@ -105,6 +109,54 @@ def record(circuits, dtypes=(QSV_C64,), max_ops=24, seed=0, log=None):
     return np.concatenate(X), np.concatenate(y).astype(np.float32), meta
 
 
+def random_blocks(count, ns=range(26, 34), ks=range(2, 7), seed=0):
+    """Random fused blocks: (n, targets, unitary) with n and k uniform, the
+    targets drawn among the lowest 8 qubits, the highest 8, or anywhere (a
+    third each), Haar-random unitaries (QR of complex Gaussians)."""
+    import workloads as W
+    rng = np.random.default_rng(seed)
+    ns, ks = list(ns), list(ks)
+    out = []
+    for _ in range(count):
+        n = int(rng.choice(ns))
+        k = int(rng.choice(ks))
+        mode = int(rng.integers(3))
+        pool = list(range(8)) if mode == 0 else list(range(n - 8, n)) if mode == 1 else list(range(n))
+        tg = [int(q) for q in rng.choice(pool, size=k, replace=False)]
+        out.append((n, tg, W.random_unitary(k, rng)))
+    return out
+
+
+def record_blocks(blocks, reps=5, log=None):
+    """Each block timed alone (median of `reps` after one warm-up) as a dense
+    gate, and for k >= 4 on complex64 as a matrix-core block."""
+    import torch
+    import workloads as W
+    X, y = [], []
+    by_n = {}
+    for b in blocks:
+        by_n.setdefault(b[0], []).append(b)
+    for n in sorted(by_n):
+        st = torch.randn(1 << n, dtype=torch.complex64, device="cuda")
+        st /= torch.linalg.vector_norm(st)
+        for _, tg, u in by_n[n]:
+            g = W.gate("UNITARY", tg)
+            g["matrix"] = u
+            kinds = [dict(mode=PLAN_PER_GATE)]
+            if len(tg) >= 4:
+                kinds.append(dict(mode=PLAN_GREEDY, kmax=len(tg), use_mfma=1))
+            for kw in kinds:
+                plan = qsv_plan_create(n, QSV_C64, [g], **kw)
+                f, sec = time_ops(plan, st, qsv_plan_stats_get(plan)["n_launches"], reps=reps)
+                X.append(f)
+                y.append(np.log(sec))
+        if log:
+            log("recorded %d blocks at n=%d" % (len(by_n[n]), n))
+        del st
+        torch.cuda.empty_cache()
+    return np.concatenate(X), np.concatenate(y).astype(np.float32)
+
+
 def init_params(rng, sizes=SIZES):
     parts = []
     for a, b in zip(sizes[:-1], sizes[1:]):
@@ -187,15 +239,20 @@ def training_circuits(ns=(24, 26, 28, 30), seed=0):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_PATH)
-    ap.add_argument("--ns", default="24,26,28,30")
+    ap.add_argument("--ns", default="26,28,30,32")
+    ap.add_argument("--blocks", type=int, default=600, help="random fused blocks (k = 2..6, n = 26..33)")
     ap.add_argument("--max-ops", type=int, default=24)
     ap.add_argument("--steps", type=int, default=3000)
     args = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)
     ns = tuple(int(x) for x in args.ns.split(","))
     t0 = time.perf_counter()
+    Xb, yb = record_blocks(random_blocks(args.blocks), log=log)
+    log("recorded %d block samples in %.1f s" % (len(yb), time.perf_counter() - t0))
     X, y, meta = record(training_circuits(ns), dtypes=(QSV_C64, QSV_C128), max_ops=args.max_ops, log=log)
-    log("recorded %d samples in %.1f s" % (len(y), time.perf_counter() - t0))
+    log("recorded %d plan-op samples in %.1f s" % (len(y), time.perf_counter() - t0))
+    X = np.concatenate([Xb, X])
+    y = np.concatenate([yb, y])
     # hold out 20% (by sample, seeded) for the prediction-error report
     rng = np.random.default_rng(0)
     perm = rng.permutation(len(y))
@@ -204,7 +261,8 @@ def main(argv=None):
     params, mean, scale, mse = train(X[tr], y[tr], steps=args.steps, log=log)
     pte = predict(params, mean, scale, X[te])
     err = float(np.median(np.abs(np.exp(pte - y[te]) - 1.0)))
-    info = {"samples": int(len(y)), "train_mse_log": mse, "heldout_median_rel_err": err, "ns": list(ns)}
+    info = {"samples": int(len(y)), "block_samples": int(len(yb)), "train_mse_log": mse,
+            "heldout_median_rel_err": err, "ns": list(ns)}
     log("train mse(log s) %.4f, held-out median relative error %.3f" % (mse, err))
     # final model on all samples
     params, mean, scale, mse = train(X, y, steps=args.steps)

@@ -61,9 +61,8 @@ __device__ inline uint64_t group_base(uint64_t g, const GroupArgs &ga) {
 
 // Work per thread: U units of VG consecutive groups.  Several independent
 // units keep enough loads in flight to cover HBM latency when a group is
-// small; when bit 0 is not a gate bit, VG = 2 consecutive groups are adjacent
-// in memory and each member access is a 16-byte (c64) or 32-byte (c128)
-// vector.  A workgroup covers U * 256 consecutive units (unit u of a thread
+// small; when bit 0 is not a gate bit, VG = 2 consecutive complex64 groups
+// are adjacent in memory and each member access is a 16-byte vector.  A workgroup covers U * 256 consecutive units (unit u of a thread
 // is 256 units after unit u - 1) and the grid covers the state once, so the
 // workgroups resident at any time stream through one contiguous window of
 // memory: on MI355X this sustains ~5.9 TB/s for in-place updates, against
@@ -387,8 +386,14 @@ static GroupArgs make_group_args(const GateAnalysis &a) {
     return ga;
 }
 
-// two consecutive groups are adjacent amplitudes when bit 0 is no gate bit
-static bool vg2(const GroupArgs &ga) { return ga.ngroups >= 2 && (ga.m == 0 || ga.lowmask[0] != 0); }
+// Two consecutive groups are adjacent amplitudes when bit 0 is no gate bit;
+// complex64 then takes them as one 16-byte access.  Complex128 members are
+// 16 bytes already, and a pair of them per thread (32-byte stride across
+// lanes) streams slower than one per thread (30 qubits, one-qubit gate on
+// qubit 12 / 22 / 29: 5.50 / 5.03 / 5.15 TB/s against 5.89 / 5.32 / 5.66).
+template <typename C> static bool vg2(const GroupArgs &ga) {
+    return sizeof(C) == 8 && ga.ngroups >= 2 && (ga.m == 0 || ga.lowmask[0] != 0);
+}
 
 template <typename C> static C to_c(const double *z) {
     C r;
@@ -411,7 +416,7 @@ static void launch_dense_m(C *psi, const GateAnalysis &a, const GroupArgs &ga, c
         for (int j = 0; j < M * M; ++j) da.mat[j] = to_c<C>(&a.mat[2 * j]);
     da.dmat = dmat;
     constexpr int UU = Unroll<C, M>::U;
-    if (!vg2(ga)) hipLaunchKernelGGL((k_dense<C, M, 1, UU>), dim3(grid_for(ga.ngroups, 256 * UU)), dim3(256), 0, s, psi, ga, da);
+    if (!vg2<C>(ga)) hipLaunchKernelGGL((k_dense<C, M, 1, UU>), dim3(grid_for(ga.ngroups, 256 * UU)), dim3(256), 0, s, psi, ga, da);
     else if (UU > 1)
         hipLaunchKernelGGL((k_dense<C, M, 2, 1>), dim3(grid_for(ga.ngroups / 2, 256)), dim3(256), 0, s, psi, ga, da);
     else hipLaunchKernelGGL((k_dense<C, M, 2, UU>), dim3(grid_for(ga.ngroups / 2, 256 * UU)), dim3(256), 0, s, psi, ga, da);
@@ -425,7 +430,7 @@ static void launch_diag_m(C *psi, const GateAnalysis &a, const GroupArgs &ga, hi
         da.offs[j] = a.offs[j];
         da.fac[j] = to_c<C>(&a.mat[2 * j]);
     }
-    if (vg2(ga))
+    if (vg2<C>(ga))
         hipLaunchKernelGGL((k_diag<C, M, 2>), dim3(grid_for(ga.ngroups / 2, 256 * DiagUnroll<C, M, 2>::U)), dim3(256), 0,
                            s, psi, ga, da);
     else
@@ -444,7 +449,7 @@ static void launch_perm_m(C *psi, const GateAnalysis &a, const GroupArgs &ga, hi
         if (a.perm_one[j]) pa.one |= 1ull << j;
     }
     constexpr int UU = Unroll<C, M>::U;
-    if (!vg2(ga)) hipLaunchKernelGGL((k_perm<C, M, 1, UU>), dim3(grid_for(ga.ngroups, 256 * UU)), dim3(256), 0, s, psi, ga, pa);
+    if (!vg2<C>(ga)) hipLaunchKernelGGL((k_perm<C, M, 1, UU>), dim3(grid_for(ga.ngroups, 256 * UU)), dim3(256), 0, s, psi, ga, pa);
     else if (UU > 1)
         hipLaunchKernelGGL((k_perm<C, M, 2, 1>), dim3(grid_for(ga.ngroups / 2, 256)), dim3(256), 0, s, psi, ga, pa);
     else hipLaunchKernelGGL((k_perm<C, M, 2, UU>), dim3(grid_for(ga.ngroups / 2, 256 * UU)), dim3(256), 0, s, psi, ga, pa);

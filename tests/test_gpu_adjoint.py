@@ -61,3 +61,43 @@ def test_gradient_with_mixed_rotations_and_controls(gpu):
     # psi is walked back to |0>
     back = psi.cpu().numpy()
     assert abs(back[0] - 1) <= 1e-12 and np.max(np.abs(back[1:])) <= 1e-12
+
+
+def _golden24():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "adjoint24_cfg4.txt")
+    energy, adj, sub = None, {}, {}
+    for line in open(path):
+        if line.startswith("# energy"):
+            energy = float(line.split()[2])
+        elif line.startswith("adjoint "):
+            _, i, g = line.split()
+            adj[int(i)] = float(g)
+        elif line.startswith("subset "):
+            _, i, ps, fd = line.split()
+            sub[int(i)] = (float(ps), float(fd))
+    return energy, np.array([adj[i] for i in range(len(adj))]), sub
+
+
+@pytest.mark.parametrize("dt,tol", [(qsv.QSV_C128, 1e-10), (qsv.QSV_C64, 1e-3)])
+def test_gradient_24q_against_oracle_golden(gpu, dt, tol):
+    """The 24-qubit hardware-efficient ansatz (12 layers, 576 angles, seed 0)
+    at its full size: every gradient entry against the oracle's adjoint,
+    and a seeded subset of 32 angles against the oracle's parameter shift and
+    central finite differences (tests/golden/adjoint24_cfg4.txt, written by
+    tests/golden/make_adjoint24.py, which calls only the oracle)."""
+    from paper_2203_08826_amd.autograd import expval
+    energy, adj, sub = _golden24()
+    circ = W.variational(24, 12, seed=0)
+    theta = _theta(circ)
+    assert theta.numel() == adj.size == 576
+    e = expval(theta, circ, 24, dtype=dt)
+    e.backward()
+    got = theta.grad.cpu().numpy()
+    assert abs(float(e.detach()) - energy) <= (1e-11 if dt == qsv.QSV_C128 else 1e-4)
+    assert np.max(np.abs(got - adj)) <= tol
+    idx = sorted(sub)
+    ps = np.array([sub[i][0] for i in idx])
+    fd = np.array([sub[i][1] for i in idx])
+    assert np.max(np.abs(got[idx] - ps)) <= tol
+    assert np.max(np.abs(got[idx] - fd)) <= max(tol, 1e-8)

@@ -233,3 +233,20 @@ def random_circuit(n, ngates, seed=0, kmax=3, max_controls=2):
             g["diag"] = random_phases(k, rng)
             c.append(g)
     return c
+
+
+def dense_windows(n, seed=0, windows=4, per=8, width=5, k=3):
+    """Dense k-qubit Haar unitaries packed into `windows` disjoint windows of
+    `width` adjacent qubits spread over the register, `per` gates per window
+    in order: a circuit where fusing each window into one wide block pays and
+    gates wider than two qubits rule out the LDS passes."""
+    rng = np.random.default_rng(seed)
+    starts = np.linspace(0, n - width, windows).astype(int)
+    c = []
+    for s in starts:
+        for _ in range(per):
+            qs = [int(s + q) for q in rng.choice(width, size=k, replace=False)]
+            g = gate("UNITARY", qs)
+            g["matrix"] = random_unitary(k, rng)
+            c.append(g)
+    return c
