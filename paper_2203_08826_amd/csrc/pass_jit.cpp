@@ -135,12 +135,33 @@ int quarter_turn(double re, double im) {
     return -1;
 }
 
+// Every exchange of the program has a local position that is a register bit
+// both before and after it (the condition for split exchanges).
+bool exchanges_split(const PassProgram &p) {
+    if (!p.pair_sigma.empty()) return false;
+    int c = p.load_part;
+    bool any = false;
+    for (auto &op : p.ops)
+        if (op.kind == POP_EXCHANGE) {
+            bool shared = false;
+            for (int i = 0; i < p.RB && !shared; ++i)
+                for (int k = 0; k < p.RB; ++k)
+                    if (p.parts[c].reg_l[i] == p.parts[op.a].reg_l[k]) shared = true;
+            if (!shared) return false;
+            any = true;
+            c = op.a;
+        }
+    return any;
+}
+
 class Gen {
   public:
     Gen(const PassProgram &p, int dtype, const JitVariant &v)
         : P(p), f32(dtype == QSV_C64), NR(1 << p.RB), pool_offset(((const PassHeaderDev *)p.blob.data())->off_pool),
           terms_offset(((const PassHeaderDev *)p.blob.data())->off_terms), share(v.share && !p.param),
-          PF(v.prefetch && pass_jit_prefetch(p, dtype)), param(p.param) {}
+          PF(v.prefetch && !(v.split && exchanges_split(p)) && pass_jit_prefetch(p, dtype)),
+          split(v.split && exchanges_split(p)),
+          param(p.param) {}
     std::string source();
 
   private:
@@ -154,6 +175,7 @@ class Gen {
     double scale_re = 1.0, scale_im = 0.0;   // complex factor owed by every amplitude of the tile (see gate())
     const bool share;     // form products of phase factors shared by several amplitudes once
     const bool PF;        // prefetch the next chunk (persistent workgroups)
+    const bool split;     // exchanges in two rounds over a shared register bit (see JitVariant)
     // Parametric kernel: matrix entries, phase angles and constant phase
     // tables are read from the program at run time (uniform loads) instead
     // of being compiled in, so the source depends only on the circuit's
@@ -572,10 +594,42 @@ std::string Gen::source() {
     // completed (the compiler waits for it) before anything after this point
     ln("__device__ __forceinline__ void hold(C v) { asm volatile(\"\" :: \"v\"(v.x), \"v\"(v.y)); }");
     ln("");
-    ln(fmt("extern \"C\" __global__ void __launch_bounds__(%d) %s(C *__restrict__ psi, const unsigned char "
-           "*__restrict__ prog, unsigned long long nchunks) {",
-           1 << P.TB, JIT_KERNEL_NAME));
-    if (any_exchange) ln(fmt("    __shared__ C lds[%d];", 1 << L));
+    // Split exchanges: a local position held in registers by both the
+    // partition before and the one after an exchange splits it into two
+    // rounds (the registers with that bit 0, then 1), each through an LDS
+    // region of half the chunk indexed with the bit removed.
+    struct Xchg {
+        int from, to, bit;   // bit: the shared register position, or -1
+    };
+    std::vector<Xchg> xs;
+    {
+        int c = P.load_part;
+        for (auto &op : P.ops)
+            if (op.kind == POP_EXCHANGE) {
+                Xchg x{c, op.a, -1};
+                if (split)
+                    for (int i = 0; i < RB && x.bit < 0; ++i)
+                        for (int k = 0; k < RB; ++k)
+                            if (P.parts[c].reg_l[i] == P.parts[op.a].reg_l[k]) {
+                                x.bit = P.parts[c].reg_l[i];
+                                break;
+                            }
+                xs.push_back(x);
+                c = op.a;
+            }
+    }
+    bool halved = !xs.empty();
+    for (auto &x : xs) halved = halved && x.bit >= 0;
+    if (split && halved)   // two workgroups of 2^TB lanes per CU: 4 waves per SIMD at 512 lanes
+        ln(fmt("extern \"C\" __global__ void __attribute__((amdgpu_flat_work_group_size(%d, %d), "
+               "amdgpu_waves_per_eu(%d))) %s(C *__restrict__ psi, const unsigned char *__restrict__ prog, "
+               "unsigned long long nchunks) {",
+               1 << P.TB, 1 << P.TB, std::max(1, (2 << P.TB) / 256), JIT_KERNEL_NAME));
+    else
+        ln(fmt("extern \"C\" __global__ void __launch_bounds__(%d) %s(C *__restrict__ psi, const unsigned char "
+               "*__restrict__ prog, unsigned long long nchunks) {",
+               1 << P.TB, JIT_KERNEL_NAME));
+    if (any_exchange) ln(fmt("    __shared__ C lds[%d];", (split && halved) ? 1 << (L - 1) : 1 << L));
     ln(fmt("    const R *pool = (const R *)(prog + %d);", pool_offset));
     ln("    (void)pool;");
     if (param) {
@@ -598,10 +652,23 @@ std::string Gen::source() {
         if (op.kind == POP_EXCHANGE) cur = op.a;
     const int final_part = cur;
     ln("    const unsigned long long lt_out = " + thread_offset(P.parts[final_part], out_pos, true) + ";");
-    if (any_exchange)
+    // compressed local index of position l when position `bit` is removed
+    auto cpos_of = [&](int bit, int *cpos) {
+        for (int l = 0; l < L; ++l) cpos[l] = (bit >= 0 && l > bit) ? l - 1 : l;
+    };
+    if (any_exchange && !(split && halved))
         for (size_t pi = 0; pi < P.parts.size(); ++pi)
             ln(fmt("    const unsigned xo%zu = swz(%s) * (unsigned)sizeof(C);", pi,
                    thread_offset(P.parts[pi], nullptr, false).c_str()));
+    if (any_exchange && split && halved)
+        for (size_t xi = 0; xi < xs.size(); ++xi) {
+            int cpos[PASS_MAX_L];
+            cpos_of(xs[xi].bit, cpos);
+            ln(fmt("    const unsigned xw%zu = swz(%s) * (unsigned)sizeof(C);", xi,
+                   thread_offset(P.parts[xs[xi].from], cpos, false).c_str()));
+            ln(fmt("    const unsigned xr%zu = swz(%s) * (unsigned)sizeof(C);", xi,
+                   thread_offset(P.parts[xs[xi].to], cpos, false).c_str()));
+        }
     // chunk base: the chunk index with zeros inserted at the local bits
     std::string cb = "    auto chunk_base = [&](unsigned long long c) { unsigned long long b = c, lo;";
     for (int l = 0; l < L; ++l)
@@ -691,6 +758,7 @@ std::string Gen::source() {
     // the ops, once per tile
     ln("    auto run_ops = [&](C *v, const unsigned long long base) __attribute__((always_inline)) {");
     cur = P.load_part;
+    int xi_next = 0;
     for (size_t o = 0; o < P.ops.size(); ++o) {
         const PassOpDev &op = P.ops[o];
         ln(fmt("        // op %zu", o));
@@ -715,6 +783,50 @@ std::string Gen::source() {
         case POP_EXCHANGE: {
             const PassPartition &A = P.parts[cur], &B = P.parts[op.a];
             const int csz = f32 ? 8 : 16;
+            if (split && halved) {
+                const Xchg &x = xs[xi_next++];
+                int cpos[PASS_MAX_L];
+                cpos_of(x.bit, cpos);
+                // the shared bit may sit at different register indices before
+                // and after: round 0's reads go to a tile of their own so they
+                // cannot overwrite registers round 1 has still to write
+                ln(fmt("        { C xt[%d];", NR));
+                for (int round = 0; round < 2; ++round) {
+                    ln("        lbar();");
+                    std::string w = "       ";
+                    for (int j = 0; j < NR; ++j) {
+                        uint32_t l = 0;
+                        bool in = true;
+                        for (int i = 0; i < RB; ++i) {
+                            const bool b = (j >> i) & 1;
+                            if (A.reg_l[i] == x.bit) in = in && (b == (round == 1));
+                            else if (b) l |= 1u << cpos[A.reg_l[i]];
+                        }
+                        if (in) w += fmt(" *(C *)((char *)lds + (xw%d ^ %uu)) = v[%d];", xi_next - 1, swz(l) * csz, j);
+                    }
+                    ln(w);
+                    ln("        lbar();");
+                    std::string r = "       ";
+                    for (int j = 0; j < NR; ++j) {
+                        uint32_t l = 0;
+                        bool in = true;
+                        for (int i = 0; i < RB; ++i) {
+                            const bool b = (j >> i) & 1;
+                            if (B.reg_l[i] == x.bit) in = in && (b == (round == 1));
+                            else if (b) l |= 1u << cpos[B.reg_l[i]];
+                        }
+                        if (in)
+                            r += fmt(" xt[%d] = *(const C *)((const char *)lds + (xr%d ^ %uu));", j, xi_next - 1,
+                                     swz(l) * csz);
+                    }
+                    ln(r);
+                }
+                std::string cp = "       ";
+                for (int j = 0; j < NR; ++j) cp += fmt(" v[%d] = xt[%d];", j, j);
+                ln(cp + " }");
+                cur = op.a;
+                break;
+            }
             ln("        lbar();");
             std::string w = "       ";
             for (int j = 0; j < NR; ++j) {
@@ -933,31 +1045,48 @@ int compile_batch(const std::vector<std::string> &srcs, std::vector<std::shared_
 }
 
 // Compiles the passes `progs` (first as their default variant `first`), all
-// kernels of a round in one program.  A kernel whose registers spill to
-// scratch is compiled again without shared phase products, then without the
-// prefetched chunk, then without both (each frees registers).  A
-// prefetching variant is kept if it spills at most a few values (measured:
-// cheaper than giving up the prefetch); else the first variant without
-// scratch, else the one with the least.
+// kernels of a round in one program.  With split exchanges requested, a
+// program whose exchanges all split is first compiled as a split kernel,
+// with and then without shared phase products; one that fits the 128
+// registers of two workgroups per CU without scratch is kept (30-qubit
+// supremacy-like circuit, complex64: 0.121 -> 0.113 s; 30-qubit QFT:
+// 14.06 -> 13.79 ms).  Otherwise a persistent prefetching kernel; one whose
+// registers spill to scratch is compiled again without shared phase
+// products, then without the prefetched chunk, then without both (each frees
+// registers).  A prefetching variant is kept if it spills at most a few
+// values (measured: cheaper than giving up the prefetch); else the first
+// variant without scratch, else the one with the least.
 int compile_pass_kernels(const std::vector<const PassProgram *> &progs, int dtype, const std::vector<std::string> &first,
-                         std::vector<std::shared_ptr<JitModule>> &out, std::string &err) {
-    const JitVariant vs[4] = {{true, true}, {false, true}, {true, false}, {false, false}};
+                         const JitVariant &first_variant, std::vector<std::shared_ptr<JitModule>> &out,
+                         std::string &err) {
+    std::vector<JitVariant> vs;
+    if (first_variant.split) {   // split variants first, then the persistent ones
+        vs.push_back(first_variant);
+        vs.push_back({false, false, true});
+    }
+    const int base = (int)vs.size();
+    vs.push_back(first_variant.split ? JitVariant{true, true, false} : first_variant);
+    vs.push_back({false, true, false});
+    vs.push_back({true, false, false});
+    vs.push_back({false, false, false});
     constexpr long SMALL_SPILL = 16;   // bytes per lane
     const size_t N = progs.size();
     out.assign(N, nullptr);
     std::vector<long> best_sc(N, -1);
     std::vector<std::vector<std::string>> tried(N);
     std::vector<char> done(N, 0);
-    for (int vi = 0; vi < 4; ++vi) {
+    for (int vi = 0; vi < (int)vs.size(); ++vi) {
         std::vector<size_t> items;
         std::vector<std::string> srcs;
         for (size_t i = 0; i < N; ++i) {
             if (done[i]) continue;
-            if (vi == 2 && out[i] && out[i]->prefetch && best_sc[i] >= 0 && best_sc[i] <= SMALL_SPILL) {
+            if (vs[vi].split && !exchanges_split(*progs[i])) continue;
+            if (vi == base + 2 && out[i] && out[i]->prefetch && best_sc[i] >= 0 && best_sc[i] <= SMALL_SPILL) {
                 done[i] = 1;
                 continue;
             }
-            std::string src = vi == 0 ? first[i] : pass_jit_source(*progs[i], dtype, vs[vi]);
+            std::string src = (vi == 0 && !(vs[0].split && !exchanges_split(*progs[i])))
+                                  ? first[i] : pass_jit_source(*progs[i], dtype, vs[vi]);
             bool seen = false;
             for (auto &t : tried[i]) seen = seen || t == src;
             if (seen) continue;
@@ -975,11 +1104,12 @@ int compile_pass_kernels(const std::vector<const PassProgram *> &progs, int dtyp
         for (size_t r = 0; r < items.size(); ++r) {
             const size_t i = items[r];
             const long sc = kernel_scratch_bytes(codes[r]->code, names[r]);
+            if (vs[vi].split && sc != 0) continue;   // split kernels only without scratch
             auto m = std::make_shared<JitModule>();
             m->code = codes[r];
             m->kernel = names[r];
             m->source = srcs[r];
-            m->prefetch = vs[vi].prefetch && pass_jit_prefetch(*progs[i], dtype);
+            m->prefetch = vs[vi].prefetch && !vs[vi].split && pass_jit_prefetch(*progs[i], dtype);
             if (!out[i] || (sc >= 0 && (best_sc[i] < 0 || sc < best_sc[i]))) {
                 out[i] = m;
                 best_sc[i] = sc;
@@ -987,6 +1117,11 @@ int compile_pass_kernels(const std::vector<const PassProgram *> &progs, int dtyp
             if (sc <= 0) done[i] = 1;   // no scratch, or a code object this parser does not read: keep it
         }
     }
+    for (size_t i = 0; i < N; ++i)
+        if (!out[i]) {
+            if (err.empty()) err = "no kernel variant of a pass compiled";
+            return -1;
+        }
     return 0;
 }
 
@@ -996,13 +1131,15 @@ int jit_compile_plan(qsv_plan *p) {
         if (op.kind == PlanOp::PASS && !op.pass->jit) progs.push_back(op.pass.get());
     if (progs.empty()) return QSV_OK;
     for (auto *pr : progs) pr->param = p->opts.jit == 2;
+    JitVariant v0;
+    v0.split = true;
     std::vector<std::string> srcs(progs.size());
     std::vector<std::shared_ptr<JitModule>> mods(progs.size());
     std::vector<size_t> todo;
     {
         std::lock_guard<std::mutex> lk(cache_mu);
         for (size_t i = 0; i < progs.size(); ++i) {
-            srcs[i] = pass_jit_source(*progs[i], p->dtype, JitVariant());
+            srcs[i] = pass_jit_source(*progs[i], p->dtype, v0);
             auto it = cache.find(srcs[i]);
             if (it != cache.end()) mods[i] = it->second;
             else todo.push_back(i);
@@ -1021,7 +1158,7 @@ int jit_compile_plan(qsv_plan *p) {
     }
     std::vector<std::shared_ptr<JitModule>> built;
     std::string err;
-    if (!uniq.empty() && compile_pass_kernels(uprogs, p->dtype, usrcs, built, err))
+    if (!uniq.empty() && compile_pass_kernels(uprogs, p->dtype, usrcs, v0, built, err))
         return fail(QSV_ERR_UNSUPPORTED, "pass kernel compilation failed: " + err);
     {
         std::lock_guard<std::mutex> lk(cache_mu);

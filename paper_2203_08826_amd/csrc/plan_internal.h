@@ -134,6 +134,11 @@ int launch_pass_jit(void *state, int n, int dtype, const PassProgram &prog, hipS
 struct JitVariant {
     bool share = true;
     bool prefetch = true;
+    // exchanges in rounds over a register bit both partitions hold (half the
+    // LDS), one chunk per workgroup and at most 128 registers per lane, so
+    // that two workgroups share a CU (no prefetch: each one's memory traffic
+    // overlaps the other's arithmetic)
+    bool split = false;
 };
 std::string pass_jit_source(const PassProgram &prog, int dtype, const JitVariant &v);
 std::string pass_jit_module_source(const PassProgram &prog);   // the source of the kernel compiled, if any
