@@ -21,6 +21,7 @@
 #include <cstring>
 #include <elf.h>
 #include <map>
+#include <set>
 #include <mutex>
 #include <unordered_map>
 
@@ -1010,9 +1011,9 @@ long kernel_scratch_bytes(const std::vector<char> &co, const std::string &kernel
 
 // Compiles several generated sources as one program: hiprtc serialises
 // compilations within a process and each costs a fixed ~0.25 s on top of
-// code generation, so the kernels of a plan share one compilation.  Kernel
-// u is renamed qsv_pass_jit_u; sources whose shared preamble (the helpers
-// before the kernel) differs go to separate programs.
+// code generation, so the kernels of a plan share one compilation.  Each
+// kernel is renamed qsv_pass_jit_<hash of its source>; sources whose shared
+// preamble (the helpers before the kernel) differs go to separate programs.
 int compile_batch(const std::vector<std::string> &srcs, std::vector<std::shared_ptr<JitCode>> &codes,
                   std::vector<std::string> &names, std::string &err) {
     const std::string marker = "extern \"C\" __global__";
@@ -1024,8 +1025,16 @@ int compile_batch(const std::vector<std::string> &srcs, std::vector<std::shared_
         const size_t k = srcs[u].find(marker);
         groups[k == std::string::npos ? std::string() : srcs[u].substr(0, k)].push_back(u);
     }
+    // kernels are named by a hash of their source (FNV-1a, 48 bits), so a
+    // profile names the same pass the same way in every process
+    auto fnv = [](const std::string &x) {
+        uint64_t h = 14695981039346656037ull;
+        for (unsigned char ch : x) h = (h ^ ch) * 1099511628211ull;
+        return h & 0xffffffffffffull;
+    };
     for (auto &g : groups) {
         std::string prog = g.first;
+        std::set<std::string> used;
         for (size_t u : g.second) {
             const std::string &src = srcs[u];
             const size_t k = src.find(marker);
@@ -1034,7 +1043,8 @@ int compile_batch(const std::vector<std::string> &srcs, std::vector<std::shared_
                 err = "generated pass source without its kernel";
                 return -1;
             }
-            names[u] = fmt("%s_%zu", JIT_KERNEL_NAME, u);
+            names[u] = fmt("%s_%012llx", JIT_KERNEL_NAME, (unsigned long long)fnv(src));
+            if (!used.insert(names[u]).second) names[u] += fmt("_%zu", u);
             prog += src.substr(k, c - k) + names[u] + "(" + src.substr(c + call.size()) + "\n";
         }
         auto code = std::make_shared<JitCode>();

@@ -102,6 +102,12 @@ struct PassHeaderDev {
     int32_t relabel;               // 1: some thread stores where another loaded
 };
 
+// The serialised layout is read back on the host by the tests (through
+// qsv_plan_op_program): keep these offsets.
+static_assert(sizeof(PassPartition) == 56 && sizeof(PassOpDev) == 112 && offsetof(PassHeaderDev, off_part) == 240 &&
+                  offsetof(PassHeaderDev, off_ops) == 244,
+              "pass program layout");
+
 struct JitModule;   // a pass program compiled into a kernel of its own (pass_jit.cpp)
 
 // Host-side pass program (what the planner emits, before serialisation).

@@ -270,3 +270,86 @@ def test_memory_stats_on_the_host():
     cur2, peak2 = qsv.qsv_memory_stats(reset_peak=True)
     assert cur2 == cur
     assert qsv.qsv_memory_stats() == (cur, cur)
+
+
+def _exchange_program(blob):
+    """(load partition, [partitions after each exchange]) of a serialised pass
+    program: header, partitions of 5 register + 9 thread positions, ops of
+    112 bytes whose kind 1 is an exchange to partition `a`."""
+    import struct
+    L, nops, npart, load_part = struct.unpack_from("<4i", blob, 0)
+    off_part, off_ops = struct.unpack_from("<2i", blob, 240)
+    parts = [(list(struct.unpack_from("<5i", blob, off_part + 56 * q)),
+              list(struct.unpack_from("<9i", blob, off_part + 56 * q + 20))) for q in range(npart)]
+    seq = []
+    for o in range(nops):
+        kind, a = struct.unpack_from("<2i", blob, off_ops + 112 * o)
+        if kind == 1:
+            seq.append(a)
+    return parts, load_part, seq
+
+
+def _local_index(part, t, j, RB, TB):
+    reg, thr = part
+    return sum(((j >> i) & 1) << reg[i] for i in range(RB)) | sum(((t >> u) & 1) << thr[u] for u in range(TB))
+
+
+@pytest.mark.parametrize("dt", [qsv.QSV_C64, qsv.QSV_C128])
+def test_compiled_exchanges_realise_their_partitions(dt):
+    """Every LDS statement of the compiled passes (split or not) simulated for
+    every lane: after the exchanges a lane's registers hold exactly the
+    amplitudes the program's last partition assigns them (partitions read
+    from the serialised program, addresses from the generated source)."""
+    import re
+
+    def swz(l):
+        return l ^ (((l >> 4) ^ (l >> 8) ^ (l >> 12)) & 15)
+
+    checked = split_seen = 0
+    for circ in (W.qft(20), W.supremacy(20, 8, seed=1), W.random_circuit(20, 150, seed=4)):
+        p = qsv.qsv_plan_create(20, dt, circ, mode=qsv.PLAN_PASSES, jit=1)
+        for i in range(p.stats()["n_launches"]):
+            if qsv.qsv_plan_op_info(p, i)["kind"] != 2:   # not an LDS pass
+                continue
+            src = qsv.qsv_plan_op_source(p, i)
+            parts, load_part, seq = _exchange_program(qsv.qsv_plan_op_program(p, i))
+            if not seq:
+                continue
+            NR = int(re.search(r"    C v\[(\d+)\];", src).group(1))
+            RB = NR.bit_length() - 1
+            T = int(re.search(r"(?:__launch_bounds__|amdgpu_flat_work_group_size)\((\d+)", src).group(1))
+            TB = T.bit_length() - 1
+            csz = 8 if dt == qsv.QSV_C64 else 16
+            offs = {}
+            for name, expr in re.findall(r"const unsigned (x[owr]\d+) = swz\((.*?)\) \* \(unsigned\)sizeof\(C\);", src):
+                pairs = [(int(u), int(q)) for u, q in re.findall(r"\(\(t >> (\d+)\) & 1u\) << (\d+)\)", expr)]
+                offs[name] = [swz(sum(((t >> u) & 1) << q for u, q in pairs)) * csz for t in range(T)]
+            v = [[_local_index(parts[load_part], t, j, RB, TB) for j in range(NR)] for t in range(T)]
+            xt = None
+            lds = {}
+            body = src[src.index("auto run_ops"):]
+            pat = re.compile(r"\*\(C \*\)\(\(char \*\)lds \+ \((x[ow]\d+) \^ (\d+)u\)\) = v\[(\d+)\];|"
+                             r"(v|xt)\[(\d+)\] = \*\(const C \*\)\(\(const char \*\)lds \+ \((x[or]\d+) \^ (\d+)u\)\);|"
+                             r"\{ C xt\[\d+\];|v\[(\d+)\] = xt\[(\d+)\];")
+            for m in pat.finditer(body):
+                if m.group(0).startswith("{ C xt"):
+                    xt = [[None] * NR for _ in range(T)]
+                    split_seen += 1
+                elif m.group(1):
+                    o, c, j = offs[m.group(1)], int(m.group(2)), int(m.group(3))
+                    for t in range(T):
+                        lds[o[t] ^ c] = v[t][j]
+                elif m.group(4):
+                    dst, j, o, c = m.group(4), int(m.group(5)), offs[m.group(6)], int(m.group(7))
+                    for t in range(T):
+                        (v if dst == "v" else xt)[t][j] = lds[o[t] ^ c]
+                else:
+                    j, k = int(m.group(8)), int(m.group(9))
+                    for t in range(T):
+                        v[t][j] = xt[t][k]
+            final = parts[seq[-1]]
+            assert all(v[t][j] == _local_index(final, t, j, RB, TB) for t in range(T) for j in range(NR)), (i, circ[0])
+            checked += 1
+    assert checked >= 4
+    if dt == qsv.QSV_C64:
+        assert split_seen >= 1
