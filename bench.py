@@ -398,10 +398,44 @@ def host_description():
     return "%s, %d logical CPUs (%d physical cores) available, %.0f GiB RAM" % (model, logical, phys, mem_kib / 2 ** 20)
 
 
-def measured_traffic(kind):
+def committed_full_run(n):
+    """The committed whole-circuit oracle run of the n-qubit QFT
+    (profiles/oracle_qft30_c128_cpu_full_run.md), or None."""
+    path = os.path.join(ROOT, "profiles", "oracle_qft%d_c128_cpu_full_run.md" % n)
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("full_run_json:"):
+            return json.loads(line.split(":", 1)[1])
+    return None
+
+
+def kernel_digest(qsv, plan):
+    """First 16 hex digits of the SHA-256 of the generated sources of a plan's
+    compiled passes, in launch order (None when it has none): what the
+    dominant kernel of a compiled plan is, independent of unrelated edits."""
+    import hashlib
+    h = hashlib.sha256()
+    count = 0
+    for i in range(qsv.qsv_plan_stats_get(plan)["n_launches"]):
+        if qsv.qsv_plan_op_info(plan, i)["kind"] == 2:
+            try:
+                src = qsv.qsv_plan_op_source(plan, i)
+            except qsv.QsvError:
+                return None
+            if not src:
+                return None   # an interpreted pass
+            h.update(src.encode())
+            count += 1
+    return h.hexdigest()[:16] if count else None
+
+
+def measured_traffic(kind, digest=None):
     """HBM bytes per launch of the dominant kernel from the committed
     FETCH_SIZE / WRITE_SIZE summary (scaled by the copy-kernel calibration),
-    or None when that summary was taken on a different version of the kernel."""
+    or None when that summary was taken on a different version of the kernel:
+    for compiled passes, other generated sources (`digest`, kernel_digest);
+    for the interpreted kernel, another version of its source file."""
     files = {"lds_pass": "lds_pass_qft30_c64_traffic.md", "lds_pass_compiled": "lds_pass_compiled_qft30_c64_traffic.md"}
     if kind not in files:
         return None
@@ -415,10 +449,14 @@ def measured_traffic(kind):
             info = json.loads(line.split(":", 1)[1])
     if info is None:
         return None
-    src = os.path.join(ROOT, info["source"])
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if sha != info["source_sha256_16"]:
-        return None
+    if "kernels_sha256_16" in info:
+        if digest != info["kernels_sha256_16"]:
+            return None
+    else:
+        src = os.path.join(ROOT, info["source"])
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        if sha != info["source_sha256_16"]:
+            return None
     return info["bytes_per_launch"]
 
 
@@ -736,7 +774,8 @@ def main():
     bytes_per_launch = d["bytes"] / d["count"]
     achieved = bytes_per_launch / avg_dur / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kind_names[dom]),
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(kind_names[dom], kernel_digest(qsv, plan)),
                 "kernel": kind_names[dom], "launches": d["count"], "avg_launch_ms": round(avg_dur * 1e3, 4),
                 "bytes_per_launch": bytes_per_launch, "per_launch_ms": per_launch_ms}
 
@@ -788,6 +827,10 @@ def main():
                          "measured; value = mean seconds per gate x %d gates" % (
                              k, n, os.environ.get("OMP_PROC_BIND", "unset"), dt_cpu, len(circ)),
                "host": host_description()}
+        full = committed_full_run(n)
+        if full is not None:   # the whole circuit, run once on this machine's host (cross-check)
+            cpu["full_run_s"] = full["s"]
+            cpu["full_run_threads"] = full["threads"]
         del a, b
 
     gbps = bytes_plan / step_s / 1e9
