@@ -54,6 +54,7 @@ struct JitModule {
     std::string kernel;                     // the kernel's name in the code object
     std::string source;                     // the pass's kernel source (as one program of its own)
     bool prefetch = false;                  // persistent workgroups with a prefetched next chunk
+    bool one_shot = false;                  // exactly one chunk per workgroup (split exchanges)
     std::mutex mu;
     struct Loaded {
         hipFunction_t fn = nullptr;
@@ -136,19 +137,53 @@ int quarter_turn(double re, double im) {
     return -1;
 }
 
-// Every exchange of the program has a local position that is a register bit
-// both before and after it (the condition for split exchanges).
+// Where a local position sits in a partition: register bit i (reg = true)
+// or thread bit i.
+struct Slot {
+    bool reg;
+    int i;
+};
+Slot slot_of(const PassPartition &part, int RB, int TB, int pos) {
+    for (int i = 0; i < RB; ++i)
+        if (part.reg_l[i] == pos) return {true, i};
+    for (int u = 0; u < TB; ++u)
+        if (part.thr_l[u] == pos) return {false, u};
+    return {true, -1};
+}
+
+// The local position an exchange from partition A to B is split on, or -1.
+// A round takes the amplitudes with that position 0 (then 1): on a side where
+// it is a register bit, half the registers of every lane; where it is a thread
+// bit, every register of half the threads.  A register bit on both sides is
+// best (no lane idles); a thread bit must lie above the 64 lanes of a wave, so
+// that whole waves idle in a round rather than half of every wave.
+int split_position(const PassProgram &p, const PassPartition &A, const PassPartition &B) {
+    for (int i = 0; i < p.RB; ++i) {   // a register bit on both sides, in A's register order
+        const Slot b = slot_of(B, p.RB, p.TB, A.reg_l[i]);
+        if (b.reg && b.i >= 0) return A.reg_l[i];
+    }
+    int best = -1, best_cost = 3;
+    for (int pos = 0; pos < p.L; ++pos) {
+        const Slot a = slot_of(A, p.RB, p.TB, pos), b = slot_of(B, p.RB, p.TB, pos);
+        if ((!a.reg && a.i < 6) || (!b.reg && b.i < 6) || (a.reg && a.i < 0) || (b.reg && b.i < 0)) continue;
+        const int cost = (a.reg ? 0 : 1) + (b.reg ? 0 : 1);
+        if (cost < best_cost) {
+            best = pos;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
+// Every exchange of the program can be split (the condition for a kernel of
+// split exchanges).
 bool exchanges_split(const PassProgram &p) {
     if (!p.pair_sigma.empty()) return false;
     int c = p.load_part;
     bool any = false;
     for (auto &op : p.ops)
         if (op.kind == POP_EXCHANGE) {
-            bool shared = false;
-            for (int i = 0; i < p.RB && !shared; ++i)
-                for (int k = 0; k < p.RB; ++k)
-                    if (p.parts[c].reg_l[i] == p.parts[op.a].reg_l[k]) shared = true;
-            if (!shared) return false;
+            if (split_position(p, p.parts[c], p.parts[op.a]) < 0) return false;
             any = true;
             c = op.a;
         }
@@ -232,11 +267,12 @@ std::string Gen::thread_offset(const PassPartition &part, const int *pos, bool g
     std::string e;
     for (int u = 0; u < P.TB; ++u) {
         const int p = pos ? pos[part.thr_l[u]] : part.thr_l[u];
+        if (p < 0) continue;   // the position an exchange is split on
         if (!e.empty()) e += " | ";
         if (global) e += fmt("((unsigned long long)((t >> %d) & 1u) << %d)", u, p);
         else e += fmt("(((t >> %d) & 1u) << %d)", u, p);
     }
-    return "(" + e + ")";
+    return e.empty() ? std::string("(0u)") : "(" + e + ")";
 }
 
 // One- or two-qubit gate on register bits (bits[0] = the matrix index MSB).
@@ -595,27 +631,18 @@ std::string Gen::source() {
     // completed (the compiler waits for it) before anything after this point
     ln("__device__ __forceinline__ void hold(C v) { asm volatile(\"\" :: \"v\"(v.x), \"v\"(v.y)); }");
     ln("");
-    // Split exchanges: a local position held in registers by both the
-    // partition before and the one after an exchange splits it into two
-    // rounds (the registers with that bit 0, then 1), each through an LDS
-    // region of half the chunk indexed with the bit removed.
+    // Split exchanges: an exchange runs in two rounds over one local
+    // position (split_position), each through an LDS region of half the
+    // chunk indexed with that position removed.
     struct Xchg {
-        int from, to, bit;   // bit: the shared register position, or -1
+        int from, to, bit;   // bit: the position split on, or -1
     };
     std::vector<Xchg> xs;
     {
         int c = P.load_part;
         for (auto &op : P.ops)
             if (op.kind == POP_EXCHANGE) {
-                Xchg x{c, op.a, -1};
-                if (split)
-                    for (int i = 0; i < RB && x.bit < 0; ++i)
-                        for (int k = 0; k < RB; ++k)
-                            if (P.parts[c].reg_l[i] == P.parts[op.a].reg_l[k]) {
-                                x.bit = P.parts[c].reg_l[i];
-                                break;
-                            }
-                xs.push_back(x);
+                xs.push_back({c, op.a, split ? split_position(P, P.parts[c], P.parts[op.a]) : -1});
                 c = op.a;
             }
     }
@@ -655,7 +682,7 @@ std::string Gen::source() {
     ln("    const unsigned long long lt_out = " + thread_offset(P.parts[final_part], out_pos, true) + ";");
     // compressed local index of position l when position `bit` is removed
     auto cpos_of = [&](int bit, int *cpos) {
-        for (int l = 0; l < L; ++l) cpos[l] = (bit >= 0 && l > bit) ? l - 1 : l;
+        for (int l = 0; l < L; ++l) cpos[l] = l == bit ? -1 : (bit >= 0 && l > bit) ? l - 1 : l;
     };
     if (any_exchange && !(split && halved))
         for (size_t pi = 0; pi < P.parts.size(); ++pi)
@@ -788,13 +815,15 @@ std::string Gen::source() {
                 const Xchg &x = xs[xi_next++];
                 int cpos[PASS_MAX_L];
                 cpos_of(x.bit, cpos);
-                // the shared bit may sit at different register indices before
-                // and after: round 0's reads go to a tile of their own so they
-                // cannot overwrite registers round 1 has still to write
+                // the split position may sit at another register index, or in
+                // the thread index, afterwards: round 0's reads go to a tile of
+                // their own so they cannot overwrite registers round 1 has
+                // still to write
+                const Slot sa = slot_of(A, RB, P.TB, x.bit), sb = slot_of(B, RB, P.TB, x.bit);
                 ln(fmt("        { C xt[%d];", NR));
                 for (int round = 0; round < 2; ++round) {
                     ln("        lbar();");
-                    std::string w = "       ";
+                    std::string w = sa.reg ? "       " : fmt("        if (((t >> %d) & 1u) == %du) {", sa.i, round);
                     for (int j = 0; j < NR; ++j) {
                         uint32_t l = 0;
                         bool in = true;
@@ -805,9 +834,9 @@ std::string Gen::source() {
                         }
                         if (in) w += fmt(" *(C *)((char *)lds + (xw%d ^ %uu)) = v[%d];", xi_next - 1, swz(l) * csz, j);
                     }
-                    ln(w);
+                    ln(sa.reg ? w : w + " }");
                     ln("        lbar();");
-                    std::string r = "       ";
+                    std::string r = sb.reg ? "       " : fmt("        if (((t >> %d) & 1u) == %du) {", sb.i, round);
                     for (int j = 0; j < NR; ++j) {
                         uint32_t l = 0;
                         bool in = true;
@@ -820,7 +849,7 @@ std::string Gen::source() {
                             r += fmt(" xt[%d] = *(const C *)((const char *)lds + (xr%d ^ %uu));", j, xi_next - 1,
                                      swz(l) * csz);
                     }
-                    ln(r);
+                    ln(sb.reg ? r : r + " }");
                 }
                 std::string cp = "       ";
                 for (int j = 0; j < NR; ++j) cp += fmt(" v[%d] = xt[%d];", j, j);
@@ -867,7 +896,12 @@ std::string Gen::source() {
     ln(fmt("    C v[%d];", NR));
     ln("    unsigned long long c = blockIdx.x;");
     if (PF) ln("    if (c < nchunks) load_chunk(v, chunk_base(c));");
-    ln("    for (; c < nchunks; c += gridDim.x) {");
+    // Split kernels take exactly one chunk per workgroup (the launch covers
+    // every chunk): without a loop the compiler has no loop-invariant values
+    // (per-thread phase factors and table entries) to hoist and hold across
+    // the whole kernel, which is what the 128-register budget cannot afford.
+    if (split && halved) ln("    if (c < nchunks) {");
+    else ln("    for (; c < nchunks; c += gridDim.x) {");
     ln(pair ? "        const unsigned long long base = pair_base(c);" : "        const unsigned long long base = chunk_base(c);");
     if (pair) {
         // chunk pairs (c, sigma(c)), moved by the workgroup of the smaller base;
@@ -1120,6 +1154,7 @@ int compile_pass_kernels(const std::vector<const PassProgram *> &progs, int dtyp
             m->kernel = names[r];
             m->source = srcs[r];
             m->prefetch = vs[vi].prefetch && !vs[vi].split && pass_jit_prefetch(*progs[i], dtype);
+            m->one_shot = vs[vi].split;   // compiled only for programs whose exchanges all split
             if (!out[i] || (sc >= 0 && (best_sc[i] < 0 || sc < best_sc[i]))) {
                 out[i] = m;
                 best_sc[i] = sc;
@@ -1216,9 +1251,6 @@ int launch_pass_jit(void *state, int n, int dtype, const PassProgram &prog, hipS
         fn = ld.fn;
         per_cu = ld.grid_per_cu;
     }
-    StagingSlot slot;
-    int st = upload_pass_program(prog, dtype, s, &slot);
-    if (st) return st;
     uint64_t nchunks = 1ull << (n - prog.L);
     if (!prog.pair_sigma.empty()) {
         uint64_t local = 0;
@@ -1227,7 +1259,15 @@ int launch_pass_jit(void *state, int n, int dtype, const PassProgram &prog, hipS
     }
     const bool pf = jm.prefetch;
     uint64_t g = pf ? (uint64_t)per_cu * device_sm_count() : std::min<uint64_t>(nchunks, 1ull << 20);
+    if (jm.one_shot) {   // one workgroup per chunk, no loop in the kernel
+        if (nchunks > 0xffffffffull >> prog.TB)
+            return fail(QSV_ERR_UNSUPPORTED, "a split-exchange pass kernel takes at most 2^32 lanes in one launch");
+        g = nchunks;
+    }
     if (g > nchunks) g = nchunks;
+    StagingSlot slot;
+    int st = upload_pass_program(prog, dtype, s, &slot);
+    if (st) return st;
     void *dprog = slot.dev;
     void *args[] = {&state, &dprog, &nchunks};
     e = hipModuleLaunchKernel(fn, (unsigned)g, 1, 1, 1u << prog.TB, 1, 1, 0, s, args, nullptr);

@@ -331,22 +331,28 @@ def test_compiled_exchanges_realise_their_partitions(dt):
             pat = re.compile(r"\*\(C \*\)\(\(char \*\)lds \+ \((x[ow]\d+) \^ (\d+)u\)\) = v\[(\d+)\];|"
                              r"(v|xt)\[(\d+)\] = \*\(const C \*\)\(\(const char \*\)lds \+ \((x[or]\d+) \^ (\d+)u\)\);|"
                              r"\{ C xt\[\d+\];|v\[(\d+)\] = xt\[(\d+)\];")
-            for m in pat.finditer(body):
-                if m.group(0).startswith("{ C xt"):
-                    xt = [[None] * NR for _ in range(T)]
-                    split_seen += 1
-                elif m.group(1):
-                    o, c, j = offs[m.group(1)], int(m.group(2)), int(m.group(3))
-                    for t in range(T):
-                        lds[o[t] ^ c] = v[t][j]
-                elif m.group(4):
-                    dst, j, o, c = m.group(4), int(m.group(5)), offs[m.group(6)], int(m.group(7))
-                    for t in range(T):
-                        (v if dst == "v" else xt)[t][j] = lds[o[t] ^ c]
-                else:
-                    j, k = int(m.group(8)), int(m.group(9))
-                    for t in range(T):
-                        v[t][j] = xt[t][k]
+            cond_pat = re.compile(r"^\s*if \(\(\(t >> (\d+)\) & 1u\) == (\d+)u\) \{")
+            for line in body.splitlines():
+                # a round of a split exchange may be limited to the threads
+                # with one bit of their index 0 (then 1): one line per round
+                cm = cond_pat.match(line)
+                ts = [t for t in range(T) if not cm or ((t >> int(cm.group(1))) & 1) == int(cm.group(2))]
+                for m in pat.finditer(line):
+                    if m.group(0).startswith("{ C xt"):
+                        xt = [[None] * NR for _ in range(T)]
+                        split_seen += 1
+                    elif m.group(1):
+                        o, c, j = offs[m.group(1)], int(m.group(2)), int(m.group(3))
+                        for t in ts:
+                            lds[o[t] ^ c] = v[t][j]
+                    elif m.group(4):
+                        dst, j, o, c = m.group(4), int(m.group(5)), offs[m.group(6)], int(m.group(7))
+                        for t in ts:
+                            (v if dst == "v" else xt)[t][j] = lds[o[t] ^ c]
+                    else:
+                        j, k = int(m.group(8)), int(m.group(9))
+                        for t in ts:
+                            v[t][j] = xt[t][k]
             final = parts[seq[-1]]
             assert all(v[t][j] == _local_index(final, t, j, RB, TB) for t in range(T) for j in range(NR)), (i, circ[0])
             checked += 1
