@@ -1092,9 +1092,8 @@ int compile_batch(const std::vector<std::string> &srcs, std::vector<std::shared_
 // kernels of a round in one program.  With split exchanges requested, a
 // program whose exchanges all split is first compiled as a split kernel,
 // with and then without shared phase products; one that fits the 128
-// registers of two workgroups per CU without scratch is kept (30-qubit
-// supremacy-like circuit, complex64: 0.121 -> 0.113 s; 30-qubit QFT:
-// 14.06 -> 13.79 ms).  Otherwise a persistent prefetching kernel; one whose
+// registers of two workgroups per CU with little scratch (SPLIT_SPILL) is
+// kept.  Otherwise a persistent prefetching kernel; one whose
 // registers spill to scratch is compiled again without shared phase
 // products, then without the prefetched chunk, then without both (each frees
 // registers).  A prefetching variant is kept if it spills at most a few
@@ -1114,6 +1113,11 @@ int compile_pass_kernels(const std::vector<const PassProgram *> &progs, int dtyp
     vs.push_back({true, false, false});
     vs.push_back({false, false, false});
     constexpr long SMALL_SPILL = 16;   // bytes per lane
+    // A split kernel is kept with up to this much scratch per lane: it has no
+    // prefetched loads for a reload to wait on (30-qubit supremacy-like
+    // circuit, complex64: 0.0953 -> 0.0909 s with two more passes split;
+    // the QFT unchanged).
+    constexpr long SPLIT_SPILL = 256;
     const size_t N = progs.size();
     out.assign(N, nullptr);
     std::vector<long> best_sc(N, -1);
@@ -1124,6 +1128,10 @@ int compile_pass_kernels(const std::vector<const PassProgram *> &progs, int dtyp
         std::vector<std::string> srcs;
         for (size_t i = 0; i < N; ++i) {
             if (done[i]) continue;
+            if (vi == base && out[i]) {   // a split kernel within SPLIT_SPILL: keep the best one
+                done[i] = 1;
+                continue;
+            }
             if (vs[vi].split && !exchanges_split(*progs[i])) continue;
             if (vi == base + 2 && out[i] && out[i]->prefetch && best_sc[i] >= 0 && best_sc[i] <= SMALL_SPILL) {
                 done[i] = 1;
@@ -1148,7 +1156,7 @@ int compile_pass_kernels(const std::vector<const PassProgram *> &progs, int dtyp
         for (size_t r = 0; r < items.size(); ++r) {
             const size_t i = items[r];
             const long sc = kernel_scratch_bytes(codes[r]->code, names[r]);
-            if (vs[vi].split && sc != 0) continue;   // split kernels only without scratch
+            if (vs[vi].split && (sc < 0 || sc > SPLIT_SPILL)) continue;
             auto m = std::make_shared<JitModule>();
             m->code = codes[r];
             m->kernel = names[r];
