@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--stream-calibration", action="store_true",
                     help="only time the in-place stream (qsv_scale) and torch's copy: the measured ceilings")
     ap.add_argument("--workload", default="qft", choices=["qft", "supremacy", "variational", "adjoint", "learned", "single_gate", "qft20",
-                             "cpu_baseline_full", "adiabatic"],
+                             "cpu_baseline_full", "adiabatic", "sliced"],
                     help="qft: the headline line; the others print their own configuration's line")
     ap.add_argument("--depth", type=int, default=20)
     ap.add_argument("--layers", type=int, default=40)
@@ -284,6 +284,68 @@ def _touched_fraction(bits, pred, line_bits=0):
         else:
             hit += bool(pred(list(o)))
     return hit / len(outs)
+
+
+def _sliced_phases(circ, n, m, a):
+    """Number of phases the sliced run cuts `circ` into: a gate whose
+    non-diagonal targets include global qubits (>= m) makes them active, and
+    a phase ends where a gate would need more than `a` active qubits."""
+    import numpy as np
+    import paper_2203_08826_amd as qsv
+    phases, cur = 1, set()
+    for g in circ:
+        mat = qsv.qsv_gate_matrix(g)
+        diag = np.count_nonzero(mat - np.diag(np.diag(mat))) == 0
+        need = set() if diag else {q for q in g["targets"] if q >= m}
+        if len(cur | need) > a:
+            phases += 1
+            cur = set(need)
+        else:
+            cur |= need
+    return phases
+
+
+def workload_sliced(args):
+    """A state in pinned host memory run through the device in slices
+    (qsv_sliced_run): the n-qubit QFT in complex64 with slices of 2^(n-4)
+    amplitudes and two active global qubits, against the same circuit with the
+    state resident in HBM; sampled amplitudes checked against the closed form."""
+    import numpy as np
+    import torch
+    import paper_2203_08826_amd as qsv
+    import workloads as W
+    from oracle import statevec as S
+    n = args.n
+    m, a = n - 4, 2
+    circ = W.qft(n)
+    x0 = W.basis_index(n, 0)
+    t0 = time.perf_counter()
+    st = torch.zeros(1 << n, dtype=torch.complex64).pin_memory()
+    alloc_s = time.perf_counter() - t0
+    _progress("sliced n=%d: pinned %.0f GiB in %.1f s" % (n, st.numel() * 8 / 2**30, alloc_s))
+    res = {}
+    for mode, name in ((qsv.PLAN_PASSES, "passes"), (qsv.PLAN_PER_GATE, "per_gate")):
+        st.zero_()
+        st[x0] = 1.0
+        t0 = time.perf_counter()
+        qsv.qsv_sliced_run(st, circ, m, a, mode=mode)
+        sec = time.perf_counter() - t0
+        ys = np.random.default_rng(3).integers(0, 1 << n, size=1 << 14)
+        err = float(np.max(np.abs(st.numpy()[ys].astype(np.complex128) - S.qft_basis_amplitudes(n, x0, ys))))
+        res[name] = {"s": round(sec, 3), "closed_form_max_abs_err": err}
+        _progress("sliced %s %.2f s" % (name, sec))
+    phases = _sliced_phases(circ, n, m, a)
+    link = 2.0 * phases * st.numel() * 8
+    for r in res.values():
+        r["host_link_GB/s"] = round(link / r["s"] / 1e9, 1)
+    del st
+    dev = torch.zeros(1 << n, dtype=torch.complex64, device="cuda")
+    dev[x0] = 1.0
+    plan = qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_PASSES, jit=1)
+    res["in_hbm_compiled_passes_s"] = round(_timed(lambda: qsv.qsv_plan_execute(plan, dev), 1), 4)
+    print(json.dumps({"metric": "seconds, state in host memory", "config": {
+        "workload": "QFT n=%d complex64 in pinned host memory, slices of 2^%d, %d active global qubits, %d phases" % (
+            n, m, a, phases)}, "pinned_alloc_s": round(alloc_s, 1), "host_link_bytes": link, "results": res}), flush=True)
 
 
 def workload_single_gate(args):
@@ -681,7 +743,8 @@ def main():
     if args.workload != "qft":
         {"supremacy": workload_supremacy, "variational": workload_variational, "adjoint": workload_adjoint,
          "learned": workload_learned, "single_gate": workload_single_gate, "qft20": workload_qft20,
-         "cpu_baseline_full": workload_cpu_baseline_full, "adiabatic": workload_adiabatic}[args.workload](args)
+         "cpu_baseline_full": workload_cpu_baseline_full, "adiabatic": workload_adiabatic,
+         "sliced": workload_sliced}[args.workload](args)
         return
 
     dev = torch.device("cuda:0")

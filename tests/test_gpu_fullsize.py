@@ -21,19 +21,34 @@ def _basis(n, x, dtype):
     return st
 
 
-@pytest.mark.parametrize("dt,mode,tol", [
-    (qsv.QSV_C64, qsv.PLAN_PASSES, 1e-5),
-    (qsv.QSV_C64, qsv.PLAN_LEARNED, 1e-5),
-    (qsv.QSV_C64, qsv.PLAN_GREEDY, 1e-5),
-    (qsv.QSV_C128, qsv.PLAN_PASSES, 1e-12),
-    (qsv.QSV_C128, qsv.PLAN_PER_GATE, 1e-12),
+@pytest.mark.parametrize("dt,mode,jit,tol", [
+    (qsv.QSV_C64, qsv.PLAN_PASSES, 0, 1e-5),
+    (qsv.QSV_C64, qsv.PLAN_PASSES, 1, 1e-5),
+    (qsv.QSV_C64, qsv.PLAN_LEARNED, 1, 1e-5),
+    (qsv.QSV_C64, qsv.PLAN_GREEDY, 0, 1e-5),
+    (qsv.QSV_C128, qsv.PLAN_PASSES, 0, 1e-12),
+    (qsv.QSV_C128, qsv.PLAN_PASSES, 1, 1e-12),
+    (qsv.QSV_C128, qsv.PLAN_PER_GATE, 0, 1e-12),
 ])
-def test_qft30_sampled_against_closed_form(gpu, dt, mode, tol):
+def test_qft30_sampled_against_closed_form(gpu, dt, mode, jit, tol):
+    """The learned case loads the shipped cost model (the headline's plan
+    choice), so it runs whichever plan the network picks."""
+    import os
     import torch
     x0 = W.basis_index(N, 0)
     tdt = torch.complex64 if dt == qsv.QSV_C64 else torch.complex128
     st = _basis(N, x0, tdt)
-    plan = qsv.qsv_plan_create(N, dt, W.qft(N), mode=mode, kmax=2)
+    if mode == qsv.PLAN_LEARNED:
+        from paper_2203_08826_amd import cost_model as CM
+        assert os.path.exists(CM.DEFAULT_PATH)
+        CM.load_into_library(CM.DEFAULT_PATH)
+    try:
+        plan = qsv.qsv_plan_create(N, dt, W.qft(N), mode=mode, kmax=2, jit=jit)
+    finally:
+        if mode == qsv.PLAN_LEARNED:
+            qsv.qsv_cost_model_clear()
+    if mode == qsv.PLAN_LEARNED:
+        assert plan.stats()["predicted_s"] > 0
     qsv.qsv_plan_execute(plan, st)
     torch.cuda.synchronize()
     ys = np.random.default_rng(11).integers(0, 1 << N, size=1 << 16)

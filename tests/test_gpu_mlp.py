@@ -34,9 +34,15 @@ def _unflat(flat, sizes):
     return out
 
 
-@pytest.mark.parametrize("batch", [1, 7, 300])
-def test_forward_backward_match_oracle(gpu, batch):
+# the shipped cost model's network (13 features -> 64 -> 64 -> 1) at the
+# batch of its training set, besides a small network at small batches
+SHIPPED = [qsv.COST_FEATURES, 64, 64, 1]
+
+
+@pytest.mark.parametrize("sizes,batch", [(SIZES, 1), (SIZES, 7), (SIZES, 300), (SHIPPED, 4800)])
+def test_forward_backward_match_oracle(gpu, sizes, batch):
     import torch
+    SIZES = sizes
     rng = np.random.default_rng(batch)
     params, flat = _init(rng, SIZES)
     params = _unflat(flat.astype(np.float64), SIZES)   # the GPU's float32 values, in float64
