@@ -274,7 +274,10 @@ __global__ void __launch_bounds__(256) k_low1(C *__restrict__ psi, Low1Args<C> a
             if (w >= a.nvec) continue;
             const uint64_t i0 = w * VEC;
             C o[VEC];
-            if (a.t < LV) {
+            // partners inside a lane's vector (only when it holds several
+            // amplitudes: with one, this branch would index the tile at run
+            // time and put it in scratch memory)
+            if (VEC > 1 && a.t < LV) {
                 const int tb = 1 << a.t;
 #pragma unroll
                 for (int j = 0; j < VEC; ++j) {
@@ -300,8 +303,11 @@ __global__ void __launch_bounds__(256) k_low1(C *__restrict__ psi, Low1Args<C> a
             }
 #pragma unroll
             for (int j = 0; j < VEC; ++j) {
+                // per component: a select of whole complex structs is lowered
+                // through scratch memory for complex128
                 const bool on = ((i0 + j) & a.cmask) == a.cmask;
-                o[j] = on ? o[j] : v[u][j];
+                o[j].x = on ? o[j].x : v[u][j].x;
+                o[j].y = on ? o[j].y : v[u][j].y;
             }
             if constexpr (VEC == 2 && sizeof(C) == 8) {
                 f4v q;
@@ -473,13 +479,11 @@ static bool try_low1(C *psi, const GateAnalysis &a, hipStream_t s) {
     la.cmask = a.cmask;
     la.nvec = (1ull << a.n) / VEC;
     la.t = t;
-    // one vector per lane in a one-shot grid (6.6 TB/s at 30 qubits against
-    // 5.4 with four per lane); two per lane once one each would exceed the
-    // 2^32 threads of a launch (33 qubits)
-    if (la.nvec / 256 <= 0xffffffffull / 256)
-        hipLaunchKernelGGL((k_low1<C, VEC, 1>), dim3(grid_for(la.nvec, 256)), dim3(256), 0, s, psi, la);
-    else
-        hipLaunchKernelGGL((k_low1<C, VEC, 2>), dim3(grid_for(la.nvec, 256 * 2)), dim3(256), 0, s, psi, la);
+    // one vector per lane (6.6 TB/s at 30 qubits against 5.4 with four per
+    // lane); beyond the 2^32 threads of a launch the capped grid strides over
+    // the state, which streams faster than two vectors per lane (33 qubits,
+    // complex128, qubit 0: 6.29 against 5.61 TB/s)
+    hipLaunchKernelGGL((k_low1<C, VEC, 1>), dim3(grid_for(la.nvec, 256)), dim3(256), 0, s, psi, la);
     return true;
 }
 
@@ -490,9 +494,12 @@ static int launch_gate_t(void *state, const GateAnalysis &a, hipStream_t s) {
     const int M = (int)a.members.size();
     if (M == 0) return QSV_OK;   // identity
     const GroupArgs ga = make_group_args(a);
-    // complex64 only: a complex128 amplitude is already a full 16-byte lane
-    // access, and the group kernel streams those faster than the shuffles
-    if (sizeof(R) == 4 && a.cls == GC_DENSE && try_low1<C, 2>(psi, a, s)) {
+    // a target below the lane span: every lane loads whole 16-byte vectors
+    // (two complex64 or one complex128 amplitude) and exchanges partners with
+    // cross-lane shuffles, where the group kernel would give each lane both
+    // members (complex128 at 33 qubits, qubits 0 and 3: 6.29 TB/s against
+    // 5.48 / 5.54)
+    if (a.cls == GC_DENSE && (sizeof(R) == 4 ? try_low1<C, 2>(psi, a, s) : try_low1<C, 1>(psi, a, s))) {
         QSV_HIP_CHECK(hipGetLastError());
         return QSV_OK;
     }
