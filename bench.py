@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--stream-calibration", action="store_true",
                     help="only time the in-place stream (qsv_scale) and torch's copy: the measured ceilings")
     ap.add_argument("--workload", default="qft", choices=["qft", "supremacy", "variational", "adjoint", "learned", "single_gate", "qft20",
-                             "cpu_baseline_full", "adiabatic", "sliced"],
+                             "cpu_baseline_full", "adiabatic", "sliced", "reductions"],
                     help="qft: the headline line; the others print their own configuration's line")
     ap.add_argument("--depth", type=int, default=20)
     ap.add_argument("--layers", type=int, default=40)
@@ -286,6 +286,75 @@ def _touched_fraction(bits, pred, line_bits=0):
     return hit / len(outs)
 
 
+def workload_reductions(args):
+    """Measurement-side kernels at n qubits (complex64 and complex128, random
+    state): probabilities of r measured qubits for several r and qubit sets,
+    the norm, the TFIM energy, a collapse, and inverse-CDF sampling of 2^20
+    shots from 2^20 outcomes; each timed with HIP events on the launch stream
+    over --steps calls, GB/s of algorithmic bytes (state read, plus outputs)."""
+    import numpy as np
+    import torch
+    import paper_2203_08826_amd as qsv
+    n = args.n
+    stream = torch.cuda.current_stream()
+    rng = np.random.default_rng(0)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / args.steps
+
+    res = {}
+    for dname, tdt, s in (("c64", torch.complex64, 8), ("c128", torch.complex128, 16)):
+        g = torch.Generator(device="cuda").manual_seed(1)
+        st = torch.randn(1 << n, dtype=tdt, device="cuda", generator=g)
+        st /= torch.linalg.vector_norm(st)
+        state_bytes = (1 << n) * s
+        cases = []
+        for r, label in ((1, "top"), (4, "low"), (10, "mixed"), (16, "mixed"), (20, "mixed"), (24, "mixed"), (n, "all")):
+            if label == "top":
+                qs = [n - 1]
+            elif label == "low":
+                qs = list(range(r))
+            elif label == "all":
+                qs = list(range(n - 1, -1, -1))
+            else:
+                qs = [int(q) for q in rng.choice(n, size=r, replace=False)]
+            out = torch.empty(1 << r, dtype=torch.float64, device="cuda")
+            cases.append(("probs_r%d_%s" % (r, label), lambda qs=qs, out=out: qsv.qsv_probabilities(st, qs, out=out),
+                          state_bytes + (1 << r) * 8))
+        nout = torch.empty(1, dtype=torch.float64, device="cuda")
+        cases.append(("norm2", lambda: qsv.qsv_norm2(st, out=nout), state_bytes))
+        cases.append(("expval_tfim", lambda: qsv.qsv_expval_zz_x(st, out=nout), state_bytes))
+        for name, fn, nbytes in cases:
+            sec = timed(fn)
+            res["%s_%s" % (name, dname)] = {"ms": round(sec * 1e3, 3), "GB/s": round(nbytes / sec / 1e9, 1)}
+            _progress("reductions %s %s %.3f ms" % (dname, name, sec * 1e3))
+        # a collapse onto one outcome of 4 qubits (reads the kept part, then rewrites the state)
+        t0 = time.perf_counter()
+        qsv.qsv_collapse(st, [0, 7, 13, n - 1], 5)
+        torch.cuda.synchronize()
+        res["collapse_r4_%s" % dname] = {"ms": round((time.perf_counter() - t0) * 1e3, 3)}
+        del st
+        torch.cuda.empty_cache()
+    # sampling: 2^20 shots from the 2^20-outcome distribution of a random state's 20 low qubits
+    probs = torch.rand(1 << 20, dtype=torch.float64, device="cuda", generator=torch.Generator(device="cuda").manual_seed(2))
+    probs /= probs.sum()
+    u = torch.rand(1 << 20, dtype=torch.float64, device="cuda", generator=torch.Generator(device="cuda").manual_seed(3))
+    sec = timed(lambda: qsv.qsv_sample_cdf(probs, u))
+    res["sample_cdf_2^20_shots_2^20_outcomes"] = {"ms": round(sec * 1e3, 3)}
+    print(json.dumps({"metric": "reduction and measurement kernels: ms and GB/s", "config": {
+        "workload": "random %d-qubit states, complex64 and complex128, %d calls each" % (n, args.steps)},
+        "peak_GB/s": HBM_PEAK_GBS, "results": res}), flush=True)
+
+
 def _sliced_phases(circ, n, m, a):
     """Number of phases the sliced run cuts `circ` into: a gate whose
     non-diagonal targets include global qubits (>= m) makes them active, and
@@ -458,6 +527,24 @@ def host_description():
         pass
     logical, phys = host_cpus()
     return "%s, %d logical CPUs (%d physical cores) available, %.0f GiB RAM" % (model, logical, phys, mem_kib / 2 ** 20)
+
+
+def exact_qft_infidelity(st, n, x0, chunk=1 << 24):
+    """1 - |<QFT|x0>, psi>|^2 / <psi, psi> over all 2^n amplitudes, the exact
+    amplitudes exp(2 pi i x0 y / 2^n) / 2^(n/2) formed in float64 chunk by
+    chunk on the device (x0 y mod 2^n is exact in int64 for n <= 31)."""
+    import torch
+    assert n <= 31
+    ov = torch.zeros((), dtype=torch.complex128, device=st.device)
+    nn = torch.zeros((), dtype=torch.float64, device=st.device)
+    for c0 in range(0, 1 << n, chunk):
+        y = torch.arange(c0, min(c0 + chunk, 1 << n), dtype=torch.int64, device=st.device)
+        ph = ((x0 * y) % (1 << n)).to(torch.float64) * (2.0 * math.pi / (1 << n))
+        ex = torch.polar(torch.full_like(ph, 2.0 ** (-n / 2)), ph)
+        a = st[c0:c0 + y.numel()].to(torch.complex128)
+        ov += torch.sum(torch.conj(ex) * a)
+        nn += torch.sum(a.real * a.real + a.imag * a.imag)
+    return float(1.0 - (ov.abs() ** 2 / nn).item())
 
 
 def committed_full_run(n):
@@ -744,7 +831,7 @@ def main():
         {"supremacy": workload_supremacy, "variational": workload_variational, "adjoint": workload_adjoint,
          "learned": workload_learned, "single_gate": workload_single_gate, "qft20": workload_qft20,
          "cpu_baseline_full": workload_cpu_baseline_full, "adiabatic": workload_adiabatic,
-         "sliced": workload_sliced}[args.workload](args)
+         "sliced": workload_sliced, "reductions": workload_reductions}[args.workload](args)
         return
 
     dev = torch.device("cuda:0")
@@ -800,6 +887,7 @@ def main():
     want = np.exp(2j * np.pi * phase) / 2 ** (n / 2)
     closed_form_err = float(np.max(np.abs(got - want)))
     c64_state = st.clone()
+    infid_exact = exact_qft_infidelity(st, n, x0)
     st = basis(torch.complex64)
     _, step_s = timed_runs(plan, st, args.steps, args.warmup)
     # the paper's dry run: the first execution including compilation
@@ -921,6 +1009,7 @@ def main():
         "dry_run_s": round(dry_s, 5),
         "first_execute_s": round(first_s, 5),
         "closed_form_max_abs_err": closed_form_err,
+        "infidelity_c64_vs_exact_all_amplitudes": infid_exact,
         "infidelity_c64_vs_c128": infid,
         "compare": compare,
         "roofline": roofline,

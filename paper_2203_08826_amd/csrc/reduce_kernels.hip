@@ -200,8 +200,6 @@ __global__ void __launch_bounds__(RT) k_probs_finish_block(const double *__restr
 
 // ---------------------------------------------------------------- TFIM energy
 
-constexpr int TB = 10;              // chunk bits: 1024 amplitudes per block in LDS
-
 struct TfimArgs {
     uint64_t N;
     int n;
@@ -216,35 +214,91 @@ __device__ inline double zz_value(uint64_t i, const TfimArgs &a) {
     return z;
 }
 
-// Per block: a chunk of 2^TB amplitudes (or the whole state if smaller) in
-// LDS.  ZZ part from the diagonal; X_q part as 2 Re sum_{bit q = 0}
-// conj(psi_i) psi_{i + 2^q}, partner from LDS for q < TB, from HBM above.
+// The energy in sweeps: a sweep holds chunks of 2^L amplitudes in LDS whose
+// local bits are the six lowest (64-amplitude runs) and a group of higher
+// ones, and sums the X_q terms of the bits q of its group (the first sweep:
+// bits 0..L-1, and every ZZ term).  Each X term is summed in exactly one
+// sweep; the state is read once per sweep (4 sweeps at 30 qubits) instead of
+// once per high qubit.
+constexpr int SWL = 12;   // local bits per sweep chunk
+struct TfimSweep {
+    TfimArgs a;
+    int L;                 // local bits of this sweep
+    int xfrom;             // local index of the first bit whose X term this sweep sums
+    int zz;                // this sweep also sums the ZZ part
+    int pos[SWL];          // global bit of local bit j (ascending)
+    uint64_t lowmask[SWL]; // (1 << pos[j]) - 1, for the chunk base
+};
+
+// Z_q Z_{q+1} summed over the open chain is (n - 1) - 2 popcount of the
+// differing neighbour bits; the periodic bond adds the top-bottom pair.
+__device__ inline double zz_closed(uint64_t i, const TfimArgs &a) {
+    const uint64_t chain = (a.n >= 2) ? ((1ull << (a.n - 1)) - 1ull) : 0ull;
+    double z = (double)(a.n - 1) - 2.0 * (double)__popcll((i ^ (i >> 1)) & chain);
+    if (a.periodic && a.n > 2) z += (((i >> (a.n - 1)) ^ i) & 1) ? -1.0 : 1.0;
+    return z;
+}
+
+// Local index l = t + RT k: thread bits 0..7 from t, register bits from k
+// (local bits 8.. of the chunk).  X pairs on register bits stay in the
+// thread's registers; pairs on thread bits read the partner from LDS.
 template <typename C>
-__global__ void __launch_bounds__(RT) k_tfim_partial(const C *__restrict__ psi, TfimArgs a, int cb,
-                                                     double *part) {
-    __shared__ C ch[1 << TB];
+__global__ void __launch_bounds__(RT) k_tfim_sweep(const C *__restrict__ psi, TfimSweep w, double *part) {
+    constexpr int KMAX = (1 << SWL) / RT;
+    __shared__ C ch[1 << SWL];
     __shared__ double sh[RT / 64];
-    const uint64_t csize = 1ull << cb;
-    const uint64_t nchunks = a.N >> cb;
+    const int csize = 1 << w.L;
+    const int K = csize >= RT ? csize / RT : 1;
+    const int t = threadIdx.x;
+    const bool live = t < csize;
+    const uint64_t nchunks = w.a.N >> w.L;
+    // global offsets of the thread's and the register's local bits
+    uint64_t off_t = 0;
+    for (int j = 0; j < w.L && j < 8; ++j) off_t |= (uint64_t)((t >> j) & 1) << w.pos[j];
+    uint64_t off_k[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        off_k[k] = 0;
+        for (int j = 8; j < w.L; ++j) off_k[k] |= (uint64_t)((k >> (j - 8)) & 1) << w.pos[j];
+    }
     double zz = 0.0, xx = 0.0;
     for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        const uint64_t base = c << cb;
-        for (uint64_t t = threadIdx.x; t < csize; t += RT) ch[t] = psi[base + t];
+        uint64_t base = c;   // chunk index with zeros inserted at the local bits
+        for (int j = 0; j < w.L; ++j) {
+            const uint64_t lo = base & w.lowmask[j];
+            base = lo | ((base ^ lo) << 1);
+        }
+        C v[KMAX];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+            if (k < K && live) v[k] = psi[base | off_t | off_k[k]];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+            if (k < K && live) ch[t + RT * k] = v[k];
         __syncthreads();
-        for (uint64_t t = threadIdx.x; t < csize; t += RT) {
-            const uint64_t i = base + t;
-            const C v = ch[t];
-            zz += abs2d(v) * zz_value(i, a);
-            for (int q = 0; q < a.n; ++q) {
-                if ((i >> q) & 1) continue;
-                const C w = (q < cb) ? ch[t | (1ull << q)] : psi[i | (1ull << q)];
-                xx += 2.0 * ((double)v.x * (double)w.x + (double)v.y * (double)w.y);
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            if (k >= K || !live) continue;
+            if (w.zz) zz += abs2d(v[k]) * zz_closed(base | off_t | off_k[k], w.a);
+            // thread bits
+            for (int j = w.xfrom; j < w.L && j < 8; ++j) {
+                if ((t >> j) & 1) continue;
+                const C u = ch[(t | (1 << j)) + RT * k];
+                xx += 2.0 * ((double)v[k].x * (double)u.x + (double)v[k].y * (double)u.y);
+            }
+            // register bits
+#pragma unroll
+            for (int r = 0; r < SWL - 8; ++r) {
+                const int j = 8 + r;
+                if (j < w.xfrom || j >= w.L || ((k >> r) & 1)) continue;
+                const C u = v[k | (1 << r)];
+                xx += 2.0 * ((double)v[k].x * (double)u.x + (double)v[k].y * (double)u.y);
             }
         }
         __syncthreads();
     }
-    const double s1 = block_sum(a.J * zz, sh);
-    const double s2 = block_sum(a.h * xx, sh);
+    const double s1 = block_sum(w.a.J * zz, sh);
+    const double s2 = block_sum(w.a.h * xx, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = s1 + s2;
 }
 
@@ -439,17 +493,40 @@ static int tfim_t(const void *state, int n, double J, double h, int periodic, do
     a.periodic = periodic;
     a.J = J;
     a.h = h;
-    const int cb = n < TB ? n : TB;
-    const uint64_t nchunks = a.N >> cb;
-    uint64_t g = nchunks;
+    // sweeps: bits 0..L0-1, then the six lowest with the next SWL - 6 bits
+    std::vector<TfimSweep> sw;
+    const int L0 = n < SWL ? n : SWL;
+    for (int first = 0; first < n;) {
+        TfimSweep w;
+        std::memset(&w, 0, sizeof(w));
+        w.a = a;
+        int L = 0;
+        if (first == 0) {
+            for (int q = 0; q < L0; ++q) w.pos[L++] = q;
+            w.xfrom = 0;
+            w.zz = 1;
+            first = L0;
+        } else {
+            for (int q = 0; q < 6; ++q) w.pos[L++] = q;
+            w.xfrom = 6;
+            for (int q = first; q < n && L < SWL; ++q) w.pos[L++] = q;
+            first += SWL - 6;
+        }
+        w.L = L;
+        for (int j = 0; j < L; ++j) w.lowmask[j] = (1ull << w.pos[j]) - 1ull;
+        sw.push_back(w);
+    }
+    uint64_t g = a.N >> L0;
     const uint64_t cap = (uint64_t)device_sm_count() * 8;
     if (g > cap) g = cap;
     StagingSlot slot;
-    int st = staging_acquire(sizeof(double) * g, &slot);
+    int st = staging_acquire(sizeof(double) * g * sw.size(), &slot);
     if (st) return st;
     double *part = (double *)slot.dev;
-    hipLaunchKernelGGL((k_tfim_partial<C>), dim3((unsigned)g), dim3(RT), 0, s, (const C *)state, a, cb, part);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, part, (int)g, 1, 1.0, out);
+    for (size_t k = 0; k < sw.size(); ++k)   // every block writes its partial (0 when it has no chunk)
+        hipLaunchKernelGGL((k_tfim_sweep<C>), dim3((unsigned)g), dim3(RT), 0, s, (const C *)state, sw[k],
+                           part + k * g);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, part, (int)(g * sw.size()), 1, 1.0, out);
     hipError_t e = hipGetLastError();
     staging_release(slot, s);
     if (e != hipSuccess) return hip_fail(e, "tfim energy launch");

@@ -58,7 +58,7 @@ def test_probabilities_ghz(gpu):
 
 
 @pytest.mark.parametrize("dt", ["c64", "c128"])
-@pytest.mark.parametrize("n", [2, 3, 9, 15])
+@pytest.mark.parametrize("n", [2, 3, 9, 15, 21])
 @pytest.mark.parametrize("periodic", [False, True])
 def test_tfim_energy_and_apply(gpu, dt, n, periodic):
     import torch
