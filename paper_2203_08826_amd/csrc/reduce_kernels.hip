@@ -125,7 +125,7 @@ struct ProbArgs {
     int P;                           // slices per job (1: write out directly)
 };
 
-constexpr int PB = 8;   // rows loaded per batch by every lane
+constexpr int PB = 8;   // rows loaded per batch by every lane (16 measured slower)
 
 template <typename C>
 __global__ void __launch_bounds__(256) k_probs(const C *__restrict__ psi, ProbArgs pa, double *__restrict__ dst) {
@@ -516,8 +516,18 @@ static int tfim_t(const void *state, int n, double J, double h, int periodic, do
         for (int j = 0; j < L; ++j) w.lowmask[j] = (1ull << w.pos[j]) - 1ull;
         sw.push_back(w);
     }
+    // exactly the workgroups that are resident at once (each walks its share
+    // of the chunks): a second, partial round of workgroups would leave most
+    // CUs idle for its duration
+    static int per_cu[2] = {0, 0};
+    int &pc = per_cu[sizeof(C) == 8 ? 0 : 1];
+    if (pc == 0) {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_tfim_sweep<C>, RT, 0) != hipSuccess || b < 1) b = 1;
+        pc = b;
+    }
     uint64_t g = a.N >> L0;
-    const uint64_t cap = (uint64_t)device_sm_count() * 8;
+    const uint64_t cap = (uint64_t)device_sm_count() * pc;
     if (g > cap) g = cap;
     StagingSlot slot;
     int st = staging_acquire(sizeof(double) * g * sw.size(), &slot);
