@@ -302,7 +302,7 @@ int qsv_probabilities(const void *state, int n, int dtype, const int *qubits, in
 /* qsv_probabilities for callers that cannot allocate (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * kernels and result, bit for bit, but the partial sums live in a fixed
- * 512 KiB device array of the library (one per GPU, kept until the process
+ * 2 MiB device array of the library (one per GPU, kept until the process
  * ends) instead of the staging ring, so the call allocates nothing -- not
  * even on its first use.  Every call on a GPU shares that array: calls that
  * overlap on one GPU (different streams, or different host threads) race

@@ -359,8 +359,11 @@ static int inner_t(const void *a, const void *b, int n, double *out, hipStream_t
 
 // Largest partial array of the probabilities reduction (doubles) and the
 // most slices a job is cut into.
-constexpr uint64_t PROB_PART_MAX = 1ull << 16;
-constexpr uint64_t PROB_SLICES_MAX = 4096;
+// Partials of one call: at most 2^18 doubles (2 MiB, the largest staging
+// span); few outcomes spread over up to 16384 slices, so that measuring a
+// handful of qubits still gives every CU dozens of waves.
+constexpr uint64_t PROB_PART_MAX = 1ull << 18;
+constexpr uint64_t PROB_SLICES_MAX = 16384;
 
 // The decomposition of a probabilities launch (host only; no HIP call).
 int prob_args(int n, const int *qubits, int r, ProbArgs *out) {
