@@ -480,10 +480,14 @@ static bool try_low1(C *psi, const GateAnalysis &a, hipStream_t s) {
     la.nvec = (1ull << a.n) / VEC;
     la.t = t;
     // one vector per lane (6.6 TB/s at 30 qubits against 5.4 with four per
-    // lane); beyond the 2^32 threads of a launch the capped grid strides over
-    // the state, which streams faster than two vectors per lane (33 qubits,
-    // complex128, qubit 0: 6.29 against 5.61 TB/s)
-    hipLaunchKernelGGL((k_low1<C, VEC, 1>), dim3(grid_for(la.nvec, 256)), dim3(256), 0, s, psi, la);
+    // lane).  Beyond the 2^32 threads of a launch (33 qubits), complex64
+    // streams best with two vectors per lane (qubit 0: 6.13 TB/s, against
+    // 5.95 with a capped grid striding over the state) and complex128 with
+    // the capped grid (6.06 / 6.29 in a probe, against 5.61 with two)
+    if (VEC == 2 && la.nvec / 256 > 0xffffffffull / 256)
+        hipLaunchKernelGGL((k_low1<C, VEC, 2>), dim3(grid_for(la.nvec, 256 * 2)), dim3(256), 0, s, psi, la);
+    else
+        hipLaunchKernelGGL((k_low1<C, VEC, 1>), dim3(grid_for(la.nvec, 256)), dim3(256), 0, s, psi, la);
     return true;
 }
 

@@ -242,29 +242,37 @@ __device__ inline double zz_closed(uint64_t i, const TfimArgs &a) {
 // Local index l = t + RT k: thread bits 0..7 from t, register bits from k
 // (local bits 8.. of the chunk).  X pairs on register bits stay in the
 // thread's registers; pairs on thread bits read the partner from LDS.
-template <typename C>
+// LT > 0: the sweep's local bits (LT), its first X bit (XF) and whether it
+// sums the ZZ part (ZZ) are compile-time constants, so every loop below
+// unrolls; LT = 0 reads them from the arguments (small states).
+template <typename C, int LT, int XF, bool ZZ>
 __global__ void __launch_bounds__(RT) k_tfim_sweep(const C *__restrict__ psi, TfimSweep w, double *part) {
     constexpr int KMAX = (1 << SWL) / RT;
     __shared__ C ch[1 << SWL];
     __shared__ double sh[RT / 64];
-    const int csize = 1 << w.L;
+    // (w itself stays unmodified: a written kernel argument would be copied
+    // to scratch memory)
+    const int L = LT > 0 ? LT : w.L;
+    const int xfrom = LT > 0 ? XF : w.xfrom;
+    const bool zzp = LT > 0 ? ZZ : (w.zz != 0);
+    const int csize = 1 << L;
     const int K = csize >= RT ? csize / RT : 1;
     const int t = threadIdx.x;
     const bool live = t < csize;
-    const uint64_t nchunks = w.a.N >> w.L;
+    const uint64_t nchunks = w.a.N >> L;
     // global offsets of the thread's and the register's local bits
     uint64_t off_t = 0;
-    for (int j = 0; j < w.L && j < 8; ++j) off_t |= (uint64_t)((t >> j) & 1) << w.pos[j];
+    for (int j = 0; j < L && j < 8; ++j) off_t |= (uint64_t)((t >> j) & 1) << w.pos[j];
     uint64_t off_k[KMAX];
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
         off_k[k] = 0;
-        for (int j = 8; j < w.L; ++j) off_k[k] |= (uint64_t)((k >> (j - 8)) & 1) << w.pos[j];
+        for (int j = 8; j < L; ++j) off_k[k] |= (uint64_t)((k >> (j - 8)) & 1) << w.pos[j];
     }
     double zz = 0.0, xx = 0.0;
     for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
         uint64_t base = c;   // chunk index with zeros inserted at the local bits
-        for (int j = 0; j < w.L; ++j) {
+        for (int j = 0; j < L; ++j) {
             const uint64_t lo = base & w.lowmask[j];
             base = lo | ((base ^ lo) << 1);
         }
@@ -279,18 +287,20 @@ __global__ void __launch_bounds__(RT) k_tfim_sweep(const C *__restrict__ psi, Tf
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
             if (k >= K || !live) continue;
-            if (w.zz) zz += abs2d(v[k]) * zz_closed(base | off_t | off_k[k], w.a);
+            if (zzp) zz += abs2d(v[k]) * zz_closed(base | off_t | off_k[k], w.a);
             // thread bits
-            for (int j = w.xfrom; j < w.L && j < 8; ++j) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (j < xfrom || j >= L) continue;
                 if ((t >> j) & 1) continue;
-                const C u = ch[(t | (1 << j)) + RT * k];
+                const C u = ch[(t | (1 << j)) + RT * k];   // (L > j: the partner exists)
                 xx += 2.0 * ((double)v[k].x * (double)u.x + (double)v[k].y * (double)u.y);
             }
             // register bits
 #pragma unroll
             for (int r = 0; r < SWL - 8; ++r) {
                 const int j = 8 + r;
-                if (j < w.xfrom || j >= w.L || ((k >> r) & 1)) continue;
+                if (j < xfrom || j >= L || ((k >> r) & 1)) continue;
                 const C u = v[k | (1 << r)];
                 xx += 2.0 * ((double)v[k].x * (double)u.x + (double)v[k].y * (double)u.y);
             }
@@ -524,10 +534,12 @@ static int tfim_t(const void *state, int n, double J, double h, int periodic, do
     // CUs idle for its duration
     static int per_cu[2] = {0, 0};
     int &pc = per_cu[sizeof(C) == 8 ? 0 : 1];
-    if (pc == 0) {
-        int b = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_tfim_sweep<C>, RT, 0) != hipSuccess || b < 1) b = 1;
-        pc = b;
+    if (pc == 0) {   // the fewest resident workgroups of the kernels the sweeps use
+        int b0 = 0, b1 = 0, b2 = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, k_tfim_sweep<C, 0, 0, false>, RT, 0) != hipSuccess) b0 = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_tfim_sweep<C, SWL, 0, true>, RT, 0) != hipSuccess) b1 = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_tfim_sweep<C, SWL, 6, false>, RT, 0) != hipSuccess) b2 = 1;
+        pc = std::max(1, std::min(b0, std::min(b1, b2)));
     }
     uint64_t g = a.N >> L0;
     const uint64_t cap = (uint64_t)device_sm_count() * pc;
@@ -536,9 +548,20 @@ static int tfim_t(const void *state, int n, double J, double h, int periodic, do
     int st = staging_acquire(sizeof(double) * g * sw.size(), &slot);
     if (st) return st;
     double *part = (double *)slot.dev;
-    for (size_t k = 0; k < sw.size(); ++k)   // every block writes its partial (0 when it has no chunk)
-        hipLaunchKernelGGL((k_tfim_sweep<C>), dim3((unsigned)g), dim3(RT), 0, s, (const C *)state, sw[k],
-                           part + k * g);
+    for (size_t k = 0; k < sw.size(); ++k) {   // every block writes its partial (0 when it has no chunk)
+        const TfimSweep &w = sw[k];
+        const dim3 G((unsigned)g), B(RT);
+        double *pk = part + k * g;
+        const C *ps = (const C *)state;
+        if (w.L == SWL && w.xfrom == 0 && w.zz) hipLaunchKernelGGL((k_tfim_sweep<C, SWL, 0, true>), G, B, 0, s, ps, w, pk);
+        else if (w.L == SWL && w.xfrom == 6 && !w.zz)
+            hipLaunchKernelGGL((k_tfim_sweep<C, SWL, 6, false>), G, B, 0, s, ps, w, pk);
+        else if (w.L == 11 && w.xfrom == 6 && !w.zz) hipLaunchKernelGGL((k_tfim_sweep<C, 11, 6, false>), G, B, 0, s, ps, w, pk);
+        else if (w.L == 10 && w.xfrom == 6 && !w.zz) hipLaunchKernelGGL((k_tfim_sweep<C, 10, 6, false>), G, B, 0, s, ps, w, pk);
+        else if (w.L == 9 && w.xfrom == 6 && !w.zz) hipLaunchKernelGGL((k_tfim_sweep<C, 9, 6, false>), G, B, 0, s, ps, w, pk);
+        else if (w.L == 8 && w.xfrom == 6 && !w.zz) hipLaunchKernelGGL((k_tfim_sweep<C, 8, 6, false>), G, B, 0, s, ps, w, pk);
+        else hipLaunchKernelGGL((k_tfim_sweep<C, 0, 0, false>), G, B, 0, s, ps, w, pk);
+    }
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, part, (int)(g * sw.size()), 1, 1.0, out);
     hipError_t e = hipGetLastError();
     staging_release(slot, s);
