@@ -2,18 +2,27 @@
 //
 // Gate fusion (Sec. 3.2 of the paper) turns runs of gates into one 2^k x 2^k
 // matrix G; applying it is the complex product Y = G X with X the state
-// viewed as 2^k rows (values tau of the target bits, targets[0] = MSB) by
-// 2^(n-k) columns (the other bits).  As a real product,
-//     [Yr; Yi] = [[Gr, -Gi], [Gi, Gr]] [Xr; Xi]        (2D x 2D, D = 2^k)
-// which runs on v_mfma_f32_32x32x2_f32 with FP32 accumulation.
+// viewed as D = 2^k rows (values tau of the target bits, targets[0] = MSB) by
+// 2^(n-k) columns (the other bits).  Two real forms run on
+// v_mfma_f32_32x32x2_f32 with FP32 accumulation:
+//   k = 4     [Yr; Yi] = [[Gr, -Gi], [Gi, Gr]] [Xr; Xi]   (one 32-row tile)
+//   k = 5, 6  T1 = Gr Xr, T2 = Gi Xi, T3 = (Gr + Gi)(Xr + Xi),
+//             Yr = T1 - T2, Yi = T3 - T1 - T2
+// The second (Gauss's three-product form of a complex product) does three
+// quarters of the matrix-core work of the first; at k >= 5 the matrix-core
+// time per column is comparable to its HBM time, so the saving is speed.
 //
 // One wave owns a tile of 32 columns.  Lane l loads X[2s + l/32][col l%32] as
-// a float2 for s < D/2 (two contiguous 256-byte rows per instruction); those
-// registers are exactly the B fragments of the K loop: step kk < D/2 takes
-// the real parts of register kk, step kk >= D/2 the imaginary parts of
-// register kk - D/2.  The real 2D x 2D matrix sits in LDS in fragment order,
-// so each A fragment is one contiguous 256-byte LDS read.  Outputs Yr and Yi
-// of the same (tau, column) land in the same lane and are stored as float2.
+// a float2 for s < D/2 (two 256-byte rows per instruction when the lowest
+// target is above bit 4); those registers are the B fragments of the K loop
+// (real parts, imaginary parts, or their sums).  The A fragments sit in LDS,
+// four fragments interleaved per lane so that one 16-byte LDS read fetches
+// four.  Outputs Yr and Yi of one (tau, column) land in the same lane and are
+// stored as a float2.  Row offsets split into a per-lane part (the row bit
+// that the lane half selects) and a wave-uniform part kept in scalar
+// registers; the LDS lane offset is re-derived in every tile so that the
+// compiler cannot hoist the fragment reads out of the tile loop (keeping all
+// of them live would cost 64-256 VGPRs and most of the occupancy).
 #include "qsv_internal.h"
 
 namespace qsv {
@@ -29,19 +38,33 @@ struct BlockArgs {
     int k;
 };
 
+// Fragments per block size: 4 * D (k = 4: 16 K-steps of the 32-row tile) or
+// 3 * (D / 32) * (D / 2) (k = 5, 6: three products, D/32 row tiles each).
+template <int K> struct MfmaShape {
+    static constexpr int D = 1 << K;
+    static constexpr int NS = D / 2;                          // float2 registers per lane
+    static constexpr int RM = K == 4 ? 1 : D / 32;            // row tiles per product
+    static constexpr int F = K == 4 ? D : NS * 3 * RM;        // A fragments
+};
+
 template <int K>
 __global__ void __launch_bounds__(MB_THREADS) k_block_mfma(float2 *__restrict__ psi, const float *__restrict__ gfrag,
                                                            BlockArgs a) {
-    constexpr int D = 1 << K;
-    constexpr int RT = (2 * D) / 32;   // row tiles of the real product
-    constexpr int NS = D / 2;          // float2 registers per lane
-    __shared__ float G[2 * D * 2 * D];
-    for (int i = threadIdx.x; i < 4 * D * D; i += MB_THREADS) G[i] = gfrag[i];
+    typedef MfmaShape<K> S;
+    constexpr int NS = S::NS, RM = S::RM, F = S::F;
+    __shared__ float4 G4[F * 16];
+    {
+        const float4 *src = (const float4 *)gfrag;
+        for (int i = threadIdx.x; i < F * 16; i += MB_THREADS) G4[i] = src[i];
+    }
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int col = lane & 31, half = lane >> 5;
+    // row 2s + half = offs[2s] + offs[half]; row tau of the outputs below has
+    // bit 2 equal to half: offs[tau] = offs[tau & ~4] + half * offs[4]
+    const uint64_t ld_half = half ? a.offs[1] : 0ull, st_half = half ? a.offs[4] : 0ull;
     const uint64_t ntiles = a.ncols >> 5;
     const uint64_t wstride = (uint64_t)gridDim.x * (MB_THREADS / 64);
     for (uint64_t tile = (uint64_t)blockIdx.x * (MB_THREADS / 64) + wave; tile < ntiles; tile += wstride) {
@@ -51,58 +74,110 @@ __global__ void __launch_bounds__(MB_THREADS) k_block_mfma(float2 *__restrict__ 
             const uint64_t lo = base & a.lowmask[b];
             base = lo | ((base ^ lo) << 1);
         }
+        int gl = lane;
+        asm volatile("" : "+v"(gl));
+        const float2 *src = psi + (base + ld_half);
         float2 x[NS];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) x[s] = psi[base + a.offs[2 * s + half]];
-        v16f acc[RT];
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-            for (int j = 0; j < 16; ++j) acc[rt][j] = 0.0f;
-#pragma unroll
-        for (int kk = 0; kk < D; ++kk) {
-            const float bf = (kk < NS) ? x[kk].x : x[kk - NS].y;
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt) {
-                const float af = G[(kk * RT + rt) * 64 + lane];
-                acc[rt] = __builtin_amdgcn_mfma_f32_32x32x2f32(af, bf, acc[rt], 0, 0, 0);
-            }
-        }
-        // row r of tile rt for accumulator j: 32 rt + 8 (j / 4) + 4 half + j % 4
+        for (int s = 0; s < NS; ++s) x[s] = src[a.offs[2 * s]];
+        float2 *dst = psi + (base + st_half);
         if constexpr (K == 4) {
+            // fragment f = K-step kk: A[r][c] = Greal[r][2 kk + c]
+            v16f acc;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int tau = 8 * (j / 4) + 4 * half + (j % 4);
-                psi[base + a.offs[tau]] = make_float2(acc[0][j], acc[0][j + 8]);
+            for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
+#pragma unroll
+            for (int f4 = 0; f4 < F / 4; ++f4) {
+                const float4 g = G4[f4 * 64 + gl];
+                const float ge[4] = {g.x, g.y, g.z, g.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int kk = 4 * f4 + e;
+                    const float bf = (kk < NS) ? x[kk].x : x[kk - NS].y;
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ge[e], bf, acc, 0, 0, 0);
+                }
             }
-        } else {
+            // accumulator j holds real row 8 (j / 4) + 4 half + j % 4: rows
+            // 0..15 are Yr, 16..31 Yi of the same tau
 #pragma unroll
-            for (int rt = 0; rt < RT / 2; ++rt)
+            for (int j = 0; j < 8; ++j) dst[a.offs[8 * (j / 4) + (j % 4)]] = make_float2(acc[j], acc[j + 8]);
+        } else {
+            // fragment f = (kk * 3 + p) * RM + rt: A[r][c] = P_p[32 rt + r][2 kk + c]
+            v16f acc[3][RM];
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int rt = 0; rt < RM; ++rt)
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) acc[p][rt][j] = 0.0f;
+#pragma unroll
+            for (int f4 = 0; f4 < F / 4; ++f4) {
+                const float4 g = G4[f4 * 64 + gl];
+                const float ge[4] = {g.x, g.y, g.z, g.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int f = 4 * f4 + e, rt = f % RM, p = (f / RM) % 3, kk = f / (3 * RM);
+                    const float bf = p == 0 ? x[kk].x : p == 1 ? x[kk].y : x[kk].x + x[kk].y;
+                    acc[p][rt] = __builtin_amdgcn_mfma_f32_32x32x2f32(ge[e], bf, acc[p][rt], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int rt = 0; rt < RM; ++rt)
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
-                    const int tau = 32 * rt + 8 * (j / 4) + 4 * half + (j % 4);
-                    psi[base + a.offs[tau]] = make_float2(acc[rt][j], acc[rt + RT / 2][j]);
+                    const float t1 = acc[0][rt][j], t2 = acc[1][rt][j], t3 = acc[2][rt][j];
+                    dst[a.offs[32 * rt + 8 * (j / 4) + (j % 4)]] = make_float2(t1 - t2, t3 - t1 - t2);
                 }
         }
     }
 }
 
-// G: complex128 row-major D x D.  Writes the real 2D x 2D matrix in MFMA
-// A-fragment order: frag[(kk * RT + rt) * 64 + l] = Greal[32 rt + l % 32][2 kk + l / 32].
+// G: complex128 row-major D x D.  Writes the A fragments of the kernel's
+// form for this k: fragment f, lane l at frag[(f / 4) * 256 + 4 l + f % 4],
+// holding A_f[l % 32][l / 32].
 static void make_fragments(const double *G, int k, float *frag) {
-    const int D = 1 << k, RT = (2 * D) / 32;
-    auto greal = [&](int r, int c) -> double {
-        const int rr = r % D, cc = c % D;
-        const double re = G[2 * (rr * D + cc)], im = G[2 * (rr * D + cc) + 1];
-        const bool top = r < D, left = c < D;
-        if (top && left) return re;
-        if (top && !left) return -im;
-        if (!top && left) return im;
-        return re;
-    };
-    for (int kk = 0; kk < D; ++kk)
-        for (int rt = 0; rt < RT; ++rt)
-            for (int l = 0; l < 64; ++l) frag[(kk * RT + rt) * 64 + l] = (float)greal(32 * rt + l % 32, 2 * kk + l / 32);
+    const int D = 1 << k;
+    auto re = [&](int r, int c) { return G[2 * (r * D + c)]; };
+    auto im = [&](int r, int c) { return G[2 * (r * D + c) + 1]; };
+    auto put = [&](int f, int l, double v) { frag[(f / 4) * 256 + 4 * l + f % 4] = (float)v; };
+    if (k == 4) {
+        // the real 2D x 2D matrix [[Gr, -Gi], [Gi, Gr]]
+        auto greal = [&](int r, int c) -> double {
+            const int rr = r % D, cc = c % D;
+            const bool top = r < D, left = c < D;
+            if (top == left) return re(rr, cc);
+            return top ? -im(rr, cc) : im(rr, cc);
+        };
+        for (int kk = 0; kk < D; ++kk)
+            for (int l = 0; l < 64; ++l) put(kk, l, greal(l % 32, 2 * kk + l / 32));
+        return;
+    }
+    const int RM = D / 32;
+    for (int kk = 0; kk < D / 2; ++kk)
+        for (int p = 0; p < 3; ++p)
+            for (int rt = 0; rt < RM; ++rt)
+                for (int l = 0; l < 64; ++l) {
+                    const int r = 32 * rt + l % 32, c = 2 * kk + l / 32;
+                    const double v = p == 0 ? re(r, c) : p == 1 ? im(r, c) : re(r, c) + im(r, c);
+                    put((kk * 3 + p) * RM + rt, l, v);
+                }
+}
+
+template <int K> static unsigned block_grid(uint64_t ntiles) {
+    // as many workgroups as can be resident, each walking tiles with a stride
+    static int resident[64] = {0};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev < 0 || dev >= 64) dev = 0;
+    if (resident[dev] == 0) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_block_mfma<K>, MB_THREADS, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        resident[dev] = per_cu;
+    }
+    const uint64_t blocks = (ntiles + 3) / 4, cap = (uint64_t)resident[dev] * device_sm_count();
+    return (unsigned)std::min(blocks, cap);
 }
 
 int launch_block_mfma(void *state, int n, const double *G, const int *targets, int k, hipStream_t s) {
@@ -122,21 +197,19 @@ int launch_block_mfma(void *state, int n, const double *G, const int *targets, i
         a.offs[t] = o;
     }
     a.ncols = 1ull << (n - k);
-    const size_t bytes = sizeof(float) * 4 * D * D;
+    const int F = k == 4 ? D : 3 * (D / 32) * (D / 2);   // MfmaShape<k>::F
+    const size_t bytes = sizeof(float) * 64 * F;
     StagingSlot slot;
     int st = staging_acquire(bytes, &slot);
     if (st) return st;
     make_fragments(G, k, (float *)slot.host);
     if ((st = staging_upload(slot, bytes, s))) return st;
     const uint64_t tiles = a.ncols >> 5;
-    uint64_t blocks = (tiles + 3) / 4;
-    const uint64_t cap = (uint64_t)device_sm_count() * 8;
-    if (blocks > cap) blocks = cap;
     const float *g = (const float *)slot.dev;
     switch (k) {
-    case 4: hipLaunchKernelGGL(k_block_mfma<4>, dim3((unsigned)blocks), dim3(MB_THREADS), 0, s, (float2 *)state, g, a); break;
-    case 5: hipLaunchKernelGGL(k_block_mfma<5>, dim3((unsigned)blocks), dim3(MB_THREADS), 0, s, (float2 *)state, g, a); break;
-    default: hipLaunchKernelGGL(k_block_mfma<6>, dim3((unsigned)blocks), dim3(MB_THREADS), 0, s, (float2 *)state, g, a); break;
+    case 4: hipLaunchKernelGGL(k_block_mfma<4>, dim3(block_grid<4>(tiles)), dim3(MB_THREADS), 0, s, (float2 *)state, g, a); break;
+    case 5: hipLaunchKernelGGL(k_block_mfma<5>, dim3(block_grid<5>(tiles)), dim3(MB_THREADS), 0, s, (float2 *)state, g, a); break;
+    default: hipLaunchKernelGGL(k_block_mfma<6>, dim3(block_grid<6>(tiles)), dim3(MB_THREADS), 0, s, (float2 *)state, g, a); break;
     }
     hipError_t e = hipGetLastError();
     staging_release(slot, s);
