@@ -24,6 +24,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_MATRIX_PEAK_TFLOPS = 157.3   # dense FP32 MFMA
 
 
 def parse():
@@ -127,6 +128,14 @@ def workload_variational(args):
     _progress("variational n=%d layers=%d: planning greedy kmax=5" % (n, args.layers))
     fused = qsv.qsv_plan_create(n, qsv.QSV_C64, circ, mode=qsv.PLAN_GREEDY, kmax=5, use_mfma=1)
     fs = fused.stats()
+    # flops the matrix cores execute: 8 * 2^k per amplitude for k = 4 (real
+    # 2D x 2D form), 6 * 2^k for k = 5, 6 (three real D x D products)
+    mfma_flops = 0.0
+    for i in range(fs["n_launches"]):
+        info = qsv.qsv_plan_op_info(fused, i)
+        if info["kind"] == 1:
+            k = int(round(math.log2(info["flops"] / (8.0 * 2.0 ** n))))
+            mfma_flops += info["flops"] * (0.75 if k >= 5 else 1.0)
     a = _zero_state(n, torch.complex64)
     qsv.qsv_plan_execute(fused, a)
     torch.cuda.synchronize()
@@ -159,7 +168,10 @@ def workload_variational(args):
         "workload": "variational n=%d layers=%d (%d gates), greedy kmax=5 on FP32 MFMA" % (n, args.layers, len(circ))},
         "fused_c64_s": round(t_fused, 4), "blocks": fs["n_blocks"], "mfma_blocks": fs["n_mfma_blocks"],
         "launches": fs["n_launches"], "GB/s": round(fs["bytes"] / t_fused / 1e9, 1),
-        "TFLOP/s": round(fs["flops"] / t_fused / 1e12, 2), "reference_c128_passes_s": round(t_ref, 4),
+        "TFLOP/s": round(fs["flops"] / t_fused / 1e12, 2),
+        "matrix_core_TFLOP/s": round(mfma_flops / t_fused / 1e12, 2),
+        "matrix_core_frac_of_fp32_peak": round(mfma_flops / t_fused / 1e12 / FP32_MATRIX_PEAK_TFLOPS, 4),
+        "reference_c128_passes_s": round(t_ref, 4),
         "infidelity_c64_vs_c128": infid,
         "passes_compiled_parametric_c64": {"s": round(t_cp, 4), "launches": cp.stats()["n_launches"],
                                            "plan_create_s": round(t_cp_create, 2),
