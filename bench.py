@@ -195,7 +195,7 @@ def workload_adjoint(args):
         th = theta.detach().clone().requires_grad_(True)
         e = expval(th, circ, n, dtype=dt)
         e.backward()
-        return float(e), th.grad.detach().cpu().numpy()
+        return float(e.detach()), th.grad.detach().cpu().numpy()
 
     fwd_bwd(qsv.QSV_C64)
     torch.cuda.synchronize()
