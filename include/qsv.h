@@ -256,8 +256,14 @@ int qsv_plan_op_gates(const qsv_plan *plan, int index, int *ids, size_t cap, siz
 void qsv_plan_destroy(qsv_plan *plan);
 
 /* Dense fused block on FP32 matrix cores (complex64 only): Y = G X with X
- * the state viewed as 2^k x 2^(n-k) (rows = target bits).  `gate` is host
- * complex64, 4^k entries; 4 <= k <= 6, no controls. */
+ * the state viewed as 2^k x 2^(n-k) (rows = target bits); the gate fusion
+ * of Sec. 3.2 widened to k qubits.  `gate` is host complex64, 4^k entries
+ * (row-major, targets[0] = the index MSB); 4 <= k <= 6, no controls,
+ * n >= k + 5, state 16-byte aligned.  k = 4 runs as one real 2D x 2D
+ * product, k = 5, 6 as three real D x D products (Yr = Gr Xr - Gi Xi,
+ * Yi = (Gr + Gi)(Xr + Xi) - Gr Xr - Gi Xi), FP32 accumulation.  Errors:
+ * QSV_ERR_UNSUPPORTED for complex128, QSV_ERR_ARITY for k or n out of range,
+ * QSV_ERR_ALIGN, QSV_ERR_NULL; the state is untouched on error. */
 int qsv_apply_block(void *state, int n, int dtype, const void *gate, const int *targets, int k, void *stream);
 
 /* One LDS pass: every gate of `gates` is applied, in order, in a single HBM
