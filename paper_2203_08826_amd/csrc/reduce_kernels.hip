@@ -218,9 +218,21 @@ __device__ inline double zz_value(uint64_t i, const TfimArgs &a) {
 // local bits are the six lowest (64-amplitude runs) and a group of higher
 // ones, and sums the X_q terms of the bits q of its group (the first sweep:
 // bits 0..L-1, and every ZZ term).  Each X term is summed in exactly one
-// sweep; the state is read once per sweep (4 sweeps at 30 qubits) instead of
-// once per high qubit.
-constexpr int SWL = 12;   // local bits per sweep chunk
+// sweep; the state is read once per sweep instead of once per high qubit.
+// Complex64 sweeps take 2^14-amplitude chunks in 1024-thread workgroups (one
+// per CU, 128 KiB of LDS, the next chunk prefetched into registers): 8 new
+// bits per sweep after the first, 3 sweeps at 30 qubits.  Complex128 takes
+// 2^12-amplitude chunks in 256-thread workgroups (4 sweeps at 30 qubits).
+constexpr int SWL = 14;   // local bits per sweep chunk, at most
+template <typename C> struct TfimShape;
+template <> struct TfimShape<float2> {
+    static constexpr int RT = 512, TB = 9, L = 13;
+    static constexpr bool PF = true;
+};
+template <> struct TfimShape<double2> {
+    static constexpr int RT = 256, TB = 8, L = 12;
+    static constexpr bool PF = false;
+};
 struct TfimSweep {
     TfimArgs a;
     int L;                 // local bits of this sweep
@@ -239,73 +251,106 @@ __device__ inline double zz_closed(uint64_t i, const TfimArgs &a) {
     return z;
 }
 
-// Local index l = t + RT k: thread bits 0..7 from t, register bits from k
-// (local bits 8.. of the chunk).  X pairs on register bits stay in the
+// Local index l = t + RT k: thread bits 0..TB-1 from t, register bits from
+// k (local bits TB.. of the chunk).  X pairs on register bits stay in the
 // thread's registers; pairs on thread bits read the partner from LDS.
 // LT > 0: the sweep's local bits (LT), its first X bit (XF) and whether it
 // sums the ZZ part (ZZ) are compile-time constants, so every loop below
 // unrolls; LT = 0 reads them from the arguments (small states).
 template <typename C, int LT, int XF, bool ZZ>
-__global__ void __launch_bounds__(RT) k_tfim_sweep(const C *__restrict__ psi, TfimSweep w, double *part) {
-    constexpr int KMAX = (1 << SWL) / RT;
-    __shared__ C ch[1 << SWL];
-    __shared__ double sh[RT / 64];
+__global__ void __launch_bounds__(TfimShape<C>::RT) __attribute__((amdgpu_waves_per_eu(4)))
+k_tfim_sweep(const C *__restrict__ psi, TfimSweep w, double *part) {
+    typedef TfimShape<C> S;
+    constexpr int RT_ = S::RT, TB = S::TB;
+    constexpr int KMAX = (1 << S::L) / RT_;
+    constexpr bool PF = S::PF && LT > 0 && !ZZ;   // the ZZ sweep has no registers to spare
+    __shared__ C ch[1 << S::L];
+    __shared__ double sh[RT_ / 64];
     // (w itself stays unmodified: a written kernel argument would be copied
     // to scratch memory)
     const int L = LT > 0 ? LT : w.L;
     const int xfrom = LT > 0 ? XF : w.xfrom;
     const bool zzp = LT > 0 ? ZZ : (w.zz != 0);
     const int csize = 1 << L;
-    const int K = csize >= RT ? csize / RT : 1;
+    const int K = csize >= RT_ ? csize / RT_ : 1;
     const int t = threadIdx.x;
     const bool live = t < csize;
     const uint64_t nchunks = w.a.N >> L;
-    // global offsets of the thread's and the register's local bits
+    // global offsets of the thread's and the register's local bits (the
+    // first sweep, CONTIG, has local bits 0..L-1: offsets t and k << TB)
+    constexpr bool CONTIG = LT > 0 && ZZ;
     uint64_t off_t = 0;
-    for (int j = 0; j < L && j < 8; ++j) off_t |= (uint64_t)((t >> j) & 1) << w.pos[j];
-    uint64_t off_k[KMAX];
+    for (int j = 0; j < L && j < TB; ++j) off_t |= (uint64_t)((t >> j) & 1) << w.pos[j];
+    uint64_t off_k[CONTIG ? 1 : KMAX];
+    if constexpr (!CONTIG) {
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
-        off_k[k] = 0;
-        for (int j = 8; j < L; ++j) off_k[k] |= (uint64_t)((k >> (j - 8)) & 1) << w.pos[j];
+        for (int k = 0; k < KMAX; ++k) {
+            off_k[k] = 0;
+            for (int j = TB; j < L; ++j) off_k[k] |= (uint64_t)((k >> (j - TB)) & 1) << w.pos[j];
+        }
     }
-    double zz = 0.0, xx = 0.0;
-    for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        uint64_t base = c;   // chunk index with zeros inserted at the local bits
+    auto offset = [&](int k) -> uint64_t {
+        if constexpr (CONTIG) return (uint64_t)t | ((uint64_t)k << TB);
+        else return off_t | off_k[k];
+    };
+    auto chunk_base = [&](uint64_t c) {   // chunk index with zeros inserted at the local bits
+        uint64_t base = c;
         for (int j = 0; j < L; ++j) {
             const uint64_t lo = base & w.lowmask[j];
             base = lo | ((base ^ lo) << 1);
         }
-        C v[KMAX];
+        return base;
+    };
+    auto load = [&](C *dst, uint64_t base) {
 #pragma unroll
         for (int k = 0; k < KMAX; ++k)
-            if (k < K && live) v[k] = psi[base | off_t | off_k[k]];
+            if (k < K && live) dst[k] = psi[base | offset(k)];
+    };
+    double zz = 0.0, xx = 0.0;
+    uint64_t c = blockIdx.x;
+    C v[KMAX];
+    if constexpr (PF) {
+        if (c < nchunks) load(v, chunk_base(c));
+    }
+    for (; c < nchunks; c += gridDim.x) {
+        const uint64_t base = chunk_base(c);
+        C vn[PF ? KMAX : 1];
+        if constexpr (PF) {
+            const uint64_t cn = c + gridDim.x;
+            if (cn < nchunks) load(vn, chunk_base(cn));
+        } else {
+            load(v, base);
+        }
 #pragma unroll
         for (int k = 0; k < KMAX; ++k)
-            if (k < K && live) ch[t + RT * k] = v[k];
+            if (k < K && live) ch[t + RT_ * k] = v[k];
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < KMAX; ++k) {
             if (k >= K || !live) continue;
-            if (zzp) zz += abs2d(v[k]) * zz_closed(base | off_t | off_k[k], w.a);
+            if (zzp) zz += abs2d(v[k]) * zz_closed(base | offset(k), w.a);
             // thread bits
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
+            for (int j = 0; j < TB; ++j) {
                 if (j < xfrom || j >= L) continue;
                 if ((t >> j) & 1) continue;
-                const C u = ch[(t | (1 << j)) + RT * k];   // (L > j: the partner exists)
+                const C u = ch[(t | (1 << j)) + RT_ * k];   // (L > j: the partner exists)
                 xx += 2.0 * ((double)v[k].x * (double)u.x + (double)v[k].y * (double)u.y);
             }
             // register bits
 #pragma unroll
-            for (int r = 0; r < SWL - 8; ++r) {
-                const int j = 8 + r;
+            for (int r = 0; r < S::L - TB; ++r) {
+                const int j = TB + r;
                 if (j < xfrom || j >= L || ((k >> r) & 1)) continue;
                 const C u = v[k | (1 << r)];
                 xx += 2.0 * ((double)v[k].x * (double)u.x + (double)v[k].y * (double)u.y);
             }
         }
         __syncthreads();
+        if constexpr (PF) {
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) v[k] = vn[k];
+        }
     }
     const double s1 = block_sum(w.a.J * zz, sh);
     const double s2 = block_sum(w.a.h * xx, sh);
@@ -498,6 +543,16 @@ static int scratch_address(double **out) {
     return QSV_OK;
 }
 
+// A later sweep: its first X bit XF = 6..LS-1 (6 plus the carried bits) as
+// a compile-time constant, by recursion over XF.
+template <typename C, int LS, int XF>
+static void launch_later_sweep(int xfrom, dim3 G, dim3 B, hipStream_t s, const C *ps, const TfimSweep &w, double *pk) {
+    if constexpr (XF >= 6) {
+        if (xfrom == XF) hipLaunchKernelGGL((k_tfim_sweep<C, LS, XF, false>), G, B, 0, s, ps, w, pk);
+        else launch_later_sweep<C, LS, XF - 1>(xfrom, G, B, s, ps, w, pk);
+    }
+}
+
 template <typename C>
 static int tfim_t(const void *state, int n, double J, double h, int periodic, double *out, hipStream_t s) {
     TfimArgs a;
@@ -506,9 +561,11 @@ static int tfim_t(const void *state, int n, double J, double h, int periodic, do
     a.periodic = periodic;
     a.J = J;
     a.h = h;
-    // sweeps: bits 0..L0-1, then the six lowest with the next SWL - 6 bits
+    // sweeps: bits 0..L0-1, then the six lowest with the next LS - 6 bits
+    typedef TfimShape<C> S;
+    constexpr int LS = S::L;
     std::vector<TfimSweep> sw;
-    const int L0 = n < SWL ? n : SWL;
+    const int L0 = n < LS ? n : LS;
     for (int first = 0; first < n;) {
         TfimSweep w;
         std::memset(&w, 0, sizeof(w));
@@ -520,10 +577,15 @@ static int tfim_t(const void *state, int n, double J, double h, int periodic, do
             w.zz = 1;
             first = L0;
         } else {
+            // the six lowest bits, then the new ones; a last sweep with fewer
+            // new bits than room keeps its full chunk shape by carrying bits
+            // just below them whose X terms an earlier sweep summed
+            const int m = std::min(n - first, LS - 6), fill = LS - 6 - m;
             for (int q = 0; q < 6; ++q) w.pos[L++] = q;
-            w.xfrom = 6;
-            for (int q = first; q < n && L < SWL; ++q) w.pos[L++] = q;
-            first += SWL - 6;
+            for (int q = first - fill; q < first; ++q) w.pos[L++] = q;
+            w.xfrom = 6 + fill;
+            for (int q = first; q < first + m; ++q) w.pos[L++] = q;
+            first += m;
         }
         w.L = L;
         for (int j = 0; j < L; ++j) w.lowmask[j] = (1ull << w.pos[j]) - 1ull;
@@ -536,9 +598,9 @@ static int tfim_t(const void *state, int n, double J, double h, int periodic, do
     int &pc = per_cu[sizeof(C) == 8 ? 0 : 1];
     if (pc == 0) {   // the fewest resident workgroups of the kernels the sweeps use
         int b0 = 0, b1 = 0, b2 = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, k_tfim_sweep<C, 0, 0, false>, RT, 0) != hipSuccess) b0 = 1;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_tfim_sweep<C, SWL, 0, true>, RT, 0) != hipSuccess) b1 = 1;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_tfim_sweep<C, SWL, 6, false>, RT, 0) != hipSuccess) b2 = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, k_tfim_sweep<C, 0, 0, false>, S::RT, 0) != hipSuccess) b0 = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_tfim_sweep<C, LS, 0, true>, S::RT, 0) != hipSuccess) b1 = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_tfim_sweep<C, LS, 6, false>, S::RT, 0) != hipSuccess) b2 = 1;
         pc = std::max(1, std::min(b0, std::min(b1, b2)));
     }
     uint64_t g = a.N >> L0;
@@ -550,16 +612,12 @@ static int tfim_t(const void *state, int n, double J, double h, int periodic, do
     double *part = (double *)slot.dev;
     for (size_t k = 0; k < sw.size(); ++k) {   // every block writes its partial (0 when it has no chunk)
         const TfimSweep &w = sw[k];
-        const dim3 G((unsigned)g), B(RT);
+        const dim3 G((unsigned)g), B(S::RT);
         double *pk = part + k * g;
         const C *ps = (const C *)state;
-        if (w.L == SWL && w.xfrom == 0 && w.zz) hipLaunchKernelGGL((k_tfim_sweep<C, SWL, 0, true>), G, B, 0, s, ps, w, pk);
-        else if (w.L == SWL && w.xfrom == 6 && !w.zz)
-            hipLaunchKernelGGL((k_tfim_sweep<C, SWL, 6, false>), G, B, 0, s, ps, w, pk);
-        else if (w.L == 11 && w.xfrom == 6 && !w.zz) hipLaunchKernelGGL((k_tfim_sweep<C, 11, 6, false>), G, B, 0, s, ps, w, pk);
-        else if (w.L == 10 && w.xfrom == 6 && !w.zz) hipLaunchKernelGGL((k_tfim_sweep<C, 10, 6, false>), G, B, 0, s, ps, w, pk);
-        else if (w.L == 9 && w.xfrom == 6 && !w.zz) hipLaunchKernelGGL((k_tfim_sweep<C, 9, 6, false>), G, B, 0, s, ps, w, pk);
-        else if (w.L == 8 && w.xfrom == 6 && !w.zz) hipLaunchKernelGGL((k_tfim_sweep<C, 8, 6, false>), G, B, 0, s, ps, w, pk);
+        if (w.L == LS && w.xfrom == 0 && w.zz) hipLaunchKernelGGL((k_tfim_sweep<C, LS, 0, true>), G, B, 0, s, ps, w, pk);
+        else if (w.L == LS && !w.zz && w.xfrom >= 6 && w.xfrom < LS)
+            launch_later_sweep<C, LS, LS - 1>(w.xfrom, G, B, s, ps, w, pk);
         else hipLaunchKernelGGL((k_tfim_sweep<C, 0, 0, false>), G, B, 0, s, ps, w, pk);
     }
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, part, (int)(g * sw.size()), 1, 1.0, out);
