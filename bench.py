@@ -301,7 +301,7 @@ def _touched_fraction(bits, pred, line_bits=0):
 def workload_reductions(args):
     """Measurement-side kernels at n qubits (complex64 and complex128, random
     state): probabilities of r measured qubits for several r and qubit sets,
-    the norm, the TFIM energy, a collapse, and inverse-CDF sampling of 2^20
+    the norm, the TFIM energy and H psi, a collapse, and inverse-CDF sampling of 2^20
     shots from 2^20 outcomes; each timed with HIP events on the launch stream
     over --steps calls, GB/s of algorithmic bytes (state read, plus outputs)."""
     import numpy as np
@@ -345,6 +345,9 @@ def workload_reductions(args):
         nout = torch.empty(1, dtype=torch.float64, device="cuda")
         cases.append(("norm2", lambda: qsv.qsv_norm2(st, out=nout), state_bytes))
         cases.append(("expval_tfim", lambda: qsv.qsv_expval_zz_x(st, out=nout), state_bytes))
+        hout = torch.empty_like(st) if n <= 32 else None   # H psi needs a second state
+        if hout is not None:
+            cases.append(("apply_tfim", lambda: qsv.qsv_apply_tfim(st, hout), 2 * state_bytes))
         for name, fn, nbytes in cases:
             sec = timed(fn)
             res["%s_%s" % (name, dname)] = {"ms": round(sec * 1e3, 3), "GB/s": round(nbytes / sec / 1e9, 1)}
@@ -354,7 +357,7 @@ def workload_reductions(args):
         qsv.qsv_collapse(st, [0, 7, 13, n - 1], 5)
         torch.cuda.synchronize()
         res["collapse_r4_%s" % dname] = {"ms": round((time.perf_counter() - t0) * 1e3, 3)}
-        del st
+        del st, hout
         torch.cuda.empty_cache()
     # sampling: 2^20 shots from the 2^20-outcome distribution of a random state's 20 low qubits
     probs = torch.rand(1 << 20, dtype=torch.float64, device="cuda", generator=torch.Generator(device="cuda").manual_seed(2))

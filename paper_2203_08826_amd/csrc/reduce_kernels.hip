@@ -228,10 +228,12 @@ template <typename C> struct TfimShape;
 template <> struct TfimShape<float2> {
     static constexpr int RT = 512, TB = 9, L = 13;
     static constexpr bool PF = true;
+    static constexpr int WPE = 4;   // waves per SIMD: two workgroups per CU
 };
 template <> struct TfimShape<double2> {
     static constexpr int RT = 256, TB = 8, L = 12;
     static constexpr bool PF = false;
+    static constexpr int WPE = 2;   // the 64 KiB chunk in LDS allows two workgroups per CU
 };
 struct TfimSweep {
     TfimArgs a;
@@ -258,7 +260,7 @@ __device__ inline double zz_closed(uint64_t i, const TfimArgs &a) {
 // sums the ZZ part (ZZ) are compile-time constants, so every loop below
 // unrolls; LT = 0 reads them from the arguments (small states).
 template <typename C, int LT, int XF, bool ZZ>
-__global__ void __launch_bounds__(TfimShape<C>::RT) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(TfimShape<C>::RT) __attribute__((amdgpu_waves_per_eu(TfimShape<C>::WPE)))
 k_tfim_sweep(const C *__restrict__ psi, TfimSweep w, double *part) {
     typedef TfimShape<C> S;
     constexpr int RT_ = S::RT, TB = S::TB;
@@ -357,24 +359,90 @@ k_tfim_sweep(const C *__restrict__ psi, TfimSweep w, double *part) {
     if (threadIdx.x == 0) part[blockIdx.x] = s1 + s2;
 }
 
-// out = H psi
-template <typename C>
-__global__ void __launch_bounds__(RT) k_apply_tfim(const C *__restrict__ psi, C *__restrict__ out, TfimArgs a) {
-    const uint64_t stride = (uint64_t)gridDim.x * RT;
-    for (uint64_t i = (uint64_t)blockIdx.x * RT + threadIdx.x; i < a.N; i += stride) {
-        const C v = psi[i];
-        const double z = a.J * zz_value(i, a);
-        double rx = z * (double)v.x, ry = z * (double)v.y;
-        double sx = 0.0, sy = 0.0;
-        for (int q = 0; q < a.n; ++q) {
-            const C w = psi[i ^ (1ull << q)];
-            sx += (double)w.x;
-            sy += (double)w.y;
+// H psi in the energy's sweeps: the first sweep writes out = J zz(i) psi_i +
+// h (sum of the partners of i on its X bits), every later sweep adds the
+// partners on its new bits (out read, added to, written back).  Sums in
+// fp64; out holds the state's type between sweeps.
+template <typename C, int LT, int XF, bool FIRST>
+__global__ void __launch_bounds__(TfimShape<C>::RT) __attribute__((amdgpu_waves_per_eu(TfimShape<C>::WPE)))
+k_apply_tfim_sweep(const C *__restrict__ psi, C *__restrict__ out, TfimSweep w) {
+    typedef TfimShape<C> S;
+    constexpr int RT_ = S::RT, TB = S::TB;
+    constexpr int KMAX = (1 << S::L) / RT_;
+    __shared__ C ch[1 << S::L];
+    const int L = LT > 0 ? LT : w.L;
+    const int xfrom = LT > 0 ? XF : w.xfrom;
+    const bool first = LT > 0 ? FIRST : (w.zz != 0);
+    const int csize = 1 << L;
+    const int K = csize >= RT_ ? csize / RT_ : 1;
+    const int t = threadIdx.x;
+    const bool live = t < csize;
+    const uint64_t nchunks = w.a.N >> L;
+    constexpr bool CONTIG = LT > 0 && FIRST;   // local bits 0..L-1
+    uint64_t off_t = 0;
+    for (int j = 0; j < L && j < TB; ++j) off_t |= (uint64_t)((t >> j) & 1) << w.pos[j];
+    uint64_t off_k[CONTIG ? 1 : KMAX];
+    if constexpr (!CONTIG) {
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            off_k[k] = 0;
+            for (int j = TB; j < L; ++j) off_k[k] |= (uint64_t)((k >> (j - TB)) & 1) << w.pos[j];
         }
-        C o;
-        o.x = (decltype(o.x))(rx + a.h * sx);
-        o.y = (decltype(o.y))(ry + a.h * sy);
-        out[i] = o;
+    }
+    auto offset = [&](int k) -> uint64_t {
+        if constexpr (CONTIG) return (uint64_t)t | ((uint64_t)k << TB);
+        else return off_t | off_k[k];
+    };
+    for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        uint64_t base = c;
+        for (int j = 0; j < L; ++j) {
+            const uint64_t lo = base & w.lowmask[j];
+            base = lo | ((base ^ lo) << 1);
+        }
+        C v[KMAX];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+            if (k < K && live) v[k] = psi[base | offset(k)];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+            if (k < K && live) ch[t + RT_ * k] = v[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            if (k >= K || !live) continue;
+            const uint64_t i = base | offset(k);
+            double ax, ay;
+            if (first) {
+                const double z = w.a.J * zz_closed(i, w.a);
+                ax = z * (double)v[k].x;
+                ay = z * (double)v[k].y;
+            } else {
+                const C o = out[i];
+                ax = (double)o.x;
+                ay = (double)o.y;
+            }
+            double sx = 0.0, sy = 0.0;
+#pragma unroll
+            for (int j = 0; j < TB; ++j) {   // thread bits: the partner from LDS
+                if (j < xfrom || j >= L) continue;
+                const C u = ch[(t ^ (1 << j)) + RT_ * k];
+                sx += (double)u.x;
+                sy += (double)u.y;
+            }
+#pragma unroll
+            for (int r = 0; r < S::L - TB; ++r) {   // register bits
+                const int j = TB + r;
+                if (j < xfrom || j >= L) continue;
+                const C u = v[k ^ (1 << r)];
+                sx += (double)u.x;
+                sy += (double)u.y;
+            }
+            C y;
+            y.x = (decltype(y.x))(ax + w.a.h * sx);
+            y.y = (decltype(y.y))(ay + w.a.h * sy);
+            out[i] = y;
+        }
+        __syncthreads();
     }
 }
 
@@ -543,25 +611,10 @@ static int scratch_address(double **out) {
     return QSV_OK;
 }
 
-// A later sweep: its first X bit XF = 6..LS-1 (6 plus the carried bits) as
-// a compile-time constant, by recursion over XF.
-template <typename C, int LS, int XF>
-static void launch_later_sweep(int xfrom, dim3 G, dim3 B, hipStream_t s, const C *ps, const TfimSweep &w, double *pk) {
-    if constexpr (XF >= 6) {
-        if (xfrom == XF) hipLaunchKernelGGL((k_tfim_sweep<C, LS, XF, false>), G, B, 0, s, ps, w, pk);
-        else launch_later_sweep<C, LS, XF - 1>(xfrom, G, B, s, ps, w, pk);
-    }
-}
-
-template <typename C>
-static int tfim_t(const void *state, int n, double J, double h, int periodic, double *out, hipStream_t s) {
-    TfimArgs a;
-    a.N = 1ull << n;
-    a.n = n;
-    a.periodic = periodic;
-    a.J = J;
-    a.h = h;
-    // sweeps: bits 0..L0-1, then the six lowest with the next LS - 6 bits
+// The sweeps of a TFIM energy or H psi: bits 0..L0-1 (with the ZZ part),
+// then the six lowest with the next LS - 6 bits.
+template <typename C> static std::vector<TfimSweep> tfim_sweeps(const TfimArgs &a) {
+    const int n = a.n;
     typedef TfimShape<C> S;
     constexpr int LS = S::L;
     std::vector<TfimSweep> sw;
@@ -591,6 +644,31 @@ static int tfim_t(const void *state, int n, double J, double h, int periodic, do
         for (int j = 0; j < L; ++j) w.lowmask[j] = (1ull << w.pos[j]) - 1ull;
         sw.push_back(w);
     }
+    return sw;
+}
+
+// A later sweep: its first X bit XF = 6..LS-1 (6 plus the carried bits) as
+// a compile-time constant, by recursion over XF.
+template <typename C, int LS, int XF>
+static void launch_later_sweep(int xfrom, dim3 G, dim3 B, hipStream_t s, const C *ps, const TfimSweep &w, double *pk) {
+    if constexpr (XF >= 6) {
+        if (xfrom == XF) hipLaunchKernelGGL((k_tfim_sweep<C, LS, XF, false>), G, B, 0, s, ps, w, pk);
+        else launch_later_sweep<C, LS, XF - 1>(xfrom, G, B, s, ps, w, pk);
+    }
+}
+
+template <typename C>
+static int tfim_t(const void *state, int n, double J, double h, int periodic, double *out, hipStream_t s) {
+    TfimArgs a;
+    a.N = 1ull << n;
+    a.n = n;
+    a.periodic = periodic;
+    a.J = J;
+    a.h = h;
+    typedef TfimShape<C> S;
+    constexpr int LS = S::L;
+    const int L0 = n < LS ? n : LS;
+    const std::vector<TfimSweep> sw = tfim_sweeps<C>(a);
     // exactly the workgroups that are resident at once (each walks its share
     // of the chunks): a second, partial round of workgroups would leave most
     // CUs idle for its duration
@@ -627,6 +705,15 @@ static int tfim_t(const void *state, int n, double J, double h, int periodic, do
     return QSV_OK;
 }
 
+// A later H psi sweep, XF = 6..LS-1 as a compile-time constant.
+template <typename C, int LS, int XF>
+static void launch_later_apply(int xfrom, dim3 G, dim3 B, hipStream_t s, const C *ps, C *po, const TfimSweep &w) {
+    if constexpr (XF >= 6) {
+        if (xfrom == XF) hipLaunchKernelGGL((k_apply_tfim_sweep<C, LS, XF, false>), G, B, 0, s, ps, po, w);
+        else launch_later_apply<C, LS, XF - 1>(xfrom, G, B, s, ps, po, w);
+    }
+}
+
 template <typename C>
 static int apply_tfim_t(const void *state, void *out, int n, double J, double h, int periodic, hipStream_t s) {
     TfimArgs a;
@@ -635,10 +722,31 @@ static int apply_tfim_t(const void *state, void *out, int n, double J, double h,
     a.periodic = periodic;
     a.J = J;
     a.h = h;
-    uint64_t g = (a.N + RT - 1) / RT;
-    const uint64_t cap = (uint64_t)device_sm_count() * 32;
+    typedef TfimShape<C> S;
+    constexpr int LS = S::L;
+    const int L0 = n < LS ? n : LS;
+    const std::vector<TfimSweep> sw = tfim_sweeps<C>(a);
+    static int per_cu[2] = {0, 0};   // resident workgroups (the fewest of the kernels used)
+    int &pc = per_cu[sizeof(C) == 8 ? 0 : 1];
+    if (pc == 0) {
+        int b0 = 0, b1 = 0, b2 = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, k_apply_tfim_sweep<C, 0, 0, false>, S::RT, 0) != hipSuccess) b0 = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_apply_tfim_sweep<C, LS, 0, true>, S::RT, 0) != hipSuccess) b1 = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_apply_tfim_sweep<C, LS, 6, false>, S::RT, 0) != hipSuccess) b2 = 1;
+        pc = std::max(1, std::min(b0, std::min(b1, b2)));
+    }
+    uint64_t g = a.N >> L0;
+    const uint64_t cap = (uint64_t)device_sm_count() * pc;
     if (g > cap) g = cap;
-    hipLaunchKernelGGL((k_apply_tfim<C>), dim3((unsigned)g), dim3(RT), 0, s, (const C *)state, (C *)out, a);
+    const dim3 G((unsigned)g), B(S::RT);
+    const C *ps = (const C *)state;
+    C *po = (C *)out;
+    for (const TfimSweep &w : sw) {   // in stream order: each later sweep adds to what the one before wrote
+        if (w.L == LS && w.xfrom == 0 && w.zz) hipLaunchKernelGGL((k_apply_tfim_sweep<C, LS, 0, true>), G, B, 0, s, ps, po, w);
+        else if (w.L == LS && !w.zz && w.xfrom >= 6 && w.xfrom < LS)
+            launch_later_apply<C, LS, LS - 1>(w.xfrom, G, B, s, ps, po, w);
+        else hipLaunchKernelGGL((k_apply_tfim_sweep<C, 0, 0, false>), G, B, 0, s, ps, po, w);
+    }
     QSV_HIP_CHECK(hipGetLastError());
     return QSV_OK;
 }
