@@ -207,23 +207,16 @@ struct TfimArgs {
     double J, h;
 };
 
-__device__ inline double zz_value(uint64_t i, const TfimArgs &a) {
-    double z = 0.0;
-    for (int q = 0; q + 1 < a.n; ++q) z += (((i >> q) ^ (i >> (q + 1))) & 1) ? -1.0 : 1.0;
-    if (a.periodic && a.n > 2) z += (((i >> (a.n - 1)) ^ i) & 1) ? -1.0 : 1.0;
-    return z;
-}
-
 // The energy in sweeps: a sweep holds chunks of 2^L amplitudes in LDS whose
 // local bits are the six lowest (64-amplitude runs) and a group of higher
 // ones, and sums the X_q terms of the bits q of its group (the first sweep:
 // bits 0..L-1, and every ZZ term).  Each X term is summed in exactly one
 // sweep; the state is read once per sweep instead of once per high qubit.
-// Complex64 sweeps take 2^14-amplitude chunks in 1024-thread workgroups (one
-// per CU, 128 KiB of LDS, the next chunk prefetched into registers): 8 new
-// bits per sweep after the first, 3 sweeps at 30 qubits.  Complex128 takes
-// 2^12-amplitude chunks in 256-thread workgroups (4 sweeps at 30 qubits).
-constexpr int SWL = 14;   // local bits per sweep chunk, at most
+// Complex64 sweeps take 2^13-amplitude chunks in 512-thread workgroups (64
+// KiB of LDS, two per CU, the next chunk prefetched into registers): 7 new
+// bits per sweep after the first.  Complex128 takes 2^12-amplitude chunks in
+// 256-thread workgroups: 6 new bits.  Either needs 4 sweeps at 30 qubits.
+constexpr int SWL = 14;   // local bits per sweep chunk, at most (the TfimSweep arrays)
 template <typename C> struct TfimShape;
 template <> struct TfimShape<float2> {
     static constexpr int RT = 512, TB = 9, L = 13;
