@@ -212,19 +212,21 @@ struct TfimArgs {
 // ones, and sums the X_q terms of the bits q of its group (the first sweep:
 // bits 0..L-1, and every ZZ term).  Each X term is summed in exactly one
 // sweep; the state is read once per sweep instead of once per high qubit.
-// Complex64 sweeps take 2^13-amplitude chunks in 512-thread workgroups (64
-// KiB of LDS, two per CU, the next chunk prefetched into registers): 7 new
-// bits per sweep after the first.  Complex128 takes 2^12-amplitude chunks in
-// 256-thread workgroups: 6 new bits.  Either needs 4 sweeps at 30 qubits.
+// The first sweep covers bits 0..11 (it also sums the ZZ part: its chunks
+// are kept small so more workgroups share a CU).  Later complex64 sweeps take
+// 2^13-amplitude chunks in 512-thread workgroups (64 KiB of LDS, two per CU,
+// the next chunk prefetched into registers): 7 new bits per sweep.
+// Complex128 takes 2^12-amplitude chunks in 256-thread workgroups: 6 new
+// bits.  Either needs 4 sweeps at 30 qubits.
 constexpr int SWL = 14;   // local bits per sweep chunk, at most (the TfimSweep arrays)
 template <typename C> struct TfimShape;
 template <> struct TfimShape<float2> {
-    static constexpr int RT = 512, TB = 9, L = 13;
+    static constexpr int RT = 512, TB = 9, L = 13, L0 = 12;   // L0: the first sweep's chunk bits
     static constexpr bool PF = true;
     static constexpr int WPE = 4;   // waves per SIMD: two workgroups per CU
 };
 template <> struct TfimShape<double2> {
-    static constexpr int RT = 256, TB = 8, L = 12;
+    static constexpr int RT = 256, TB = 8, L = 12, L0 = 12;
     static constexpr bool PF = false;
     static constexpr int WPE = 2;   // the 64 KiB chunk in LDS allows two workgroups per CU
 };
@@ -259,7 +261,7 @@ k_tfim_sweep(const C *__restrict__ psi, TfimSweep w, double *part) {
     constexpr int RT_ = S::RT, TB = S::TB;
     constexpr int KMAX = (1 << S::L) / RT_;
     constexpr bool PF = S::PF && LT > 0 && !ZZ;   // the ZZ sweep has no registers to spare
-    __shared__ C ch[1 << S::L];
+    __shared__ C ch[1 << (LT > 0 ? LT : S::L)];
     __shared__ double sh[RT_ / 64];
     // (w itself stays unmodified: a written kernel argument would be copied
     // to scratch memory)
@@ -362,7 +364,7 @@ k_apply_tfim_sweep(const C *__restrict__ psi, C *__restrict__ out, TfimSweep w) 
     typedef TfimShape<C> S;
     constexpr int RT_ = S::RT, TB = S::TB;
     constexpr int KMAX = (1 << S::L) / RT_;
-    __shared__ C ch[1 << S::L];
+    __shared__ C ch[1 << (LT > 0 ? LT : S::L)];
     const int L = LT > 0 ? LT : w.L;
     const int xfrom = LT > 0 ? XF : w.xfrom;
     const bool first = LT > 0 ? FIRST : (w.zz != 0);
@@ -611,7 +613,7 @@ template <typename C> static std::vector<TfimSweep> tfim_sweeps(const TfimArgs &
     typedef TfimShape<C> S;
     constexpr int LS = S::L;
     std::vector<TfimSweep> sw;
-    const int L0 = n < LS ? n : LS;
+    const int L0 = n < S::L0 ? n : S::L0;
     for (int first = 0; first < n;) {
         TfimSweep w;
         std::memset(&w, 0, sizeof(w));
@@ -660,38 +662,42 @@ static int tfim_t(const void *state, int n, double J, double h, int periodic, do
     a.h = h;
     typedef TfimShape<C> S;
     constexpr int LS = S::L;
-    const int L0 = n < LS ? n : LS;
     const std::vector<TfimSweep> sw = tfim_sweeps<C>(a);
-    // exactly the workgroups that are resident at once (each walks its share
-    // of the chunks): a second, partial round of workgroups would leave most
-    // CUs idle for its duration
-    static int per_cu[2] = {0, 0};
-    int &pc = per_cu[sizeof(C) == 8 ? 0 : 1];
-    if (pc == 0) {   // the fewest resident workgroups of the kernels the sweeps use
-        int b0 = 0, b1 = 0, b2 = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, k_tfim_sweep<C, 0, 0, false>, S::RT, 0) != hipSuccess) b0 = 1;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_tfim_sweep<C, LS, 0, true>, S::RT, 0) != hipSuccess) b1 = 1;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_tfim_sweep<C, LS, 6, false>, S::RT, 0) != hipSuccess) b2 = 1;
-        pc = std::max(1, std::min(b0, std::min(b1, b2)));
+    // per sweep, exactly the workgroups of its kernel that are resident at
+    // once (each walks its share of the chunks): a second, partial round of
+    // workgroups would leave most CUs idle for its duration
+    static int per_cu[2][3] = {{0, 0, 0}, {0, 0, 0}};   // [dtype][generic, first, later]
+    int *pc = per_cu[sizeof(C) == 8 ? 0 : 1];
+    if (pc[0] == 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc[0], k_tfim_sweep<C, 0, 0, false>, S::RT, 0) != hipSuccess) pc[0] = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc[1], k_tfim_sweep<C, S::L0, 0, true>, S::RT, 0) != hipSuccess) pc[1] = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc[2], k_tfim_sweep<C, LS, 6, false>, S::RT, 0) != hipSuccess) pc[2] = 1;
+        for (int i = 0; i < 3; ++i) pc[i] = std::max(1, pc[i]);
     }
-    uint64_t g = a.N >> L0;
-    const uint64_t cap = (uint64_t)device_sm_count() * pc;
-    if (g > cap) g = cap;
+    std::vector<uint64_t> gs(sw.size()), offs(sw.size());
+    uint64_t total = 0;
+    for (size_t k = 0; k < sw.size(); ++k) {
+        const TfimSweep &w = sw[k];
+        const int kind = (w.L == S::L0 && w.xfrom == 0 && w.zz) ? 1 : (w.L == LS && !w.zz && w.xfrom >= 6 && w.xfrom < LS) ? 2 : 0;
+        gs[k] = std::min<uint64_t>(a.N >> w.L, (uint64_t)device_sm_count() * pc[kind]);
+        offs[k] = total;
+        total += gs[k];
+    }
     StagingSlot slot;
-    int st = staging_acquire(sizeof(double) * g * sw.size(), &slot);
+    int st = staging_acquire(sizeof(double) * total, &slot);
     if (st) return st;
     double *part = (double *)slot.dev;
     for (size_t k = 0; k < sw.size(); ++k) {   // every block writes its partial (0 when it has no chunk)
         const TfimSweep &w = sw[k];
-        const dim3 G((unsigned)g), B(S::RT);
-        double *pk = part + k * g;
+        const dim3 G((unsigned)gs[k]), B(S::RT);
+        double *pk = part + offs[k];
         const C *ps = (const C *)state;
-        if (w.L == LS && w.xfrom == 0 && w.zz) hipLaunchKernelGGL((k_tfim_sweep<C, LS, 0, true>), G, B, 0, s, ps, w, pk);
+        if (w.L == S::L0 && w.xfrom == 0 && w.zz) hipLaunchKernelGGL((k_tfim_sweep<C, S::L0, 0, true>), G, B, 0, s, ps, w, pk);
         else if (w.L == LS && !w.zz && w.xfrom >= 6 && w.xfrom < LS)
             launch_later_sweep<C, LS, LS - 1>(w.xfrom, G, B, s, ps, w, pk);
         else hipLaunchKernelGGL((k_tfim_sweep<C, 0, 0, false>), G, B, 0, s, ps, w, pk);
     }
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, part, (int)(g * sw.size()), 1, 1.0, out);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, part, (int)total, 1, 1.0, out);
     hipError_t e = hipGetLastError();
     staging_release(slot, s);
     if (e != hipSuccess) return hip_fail(e, "tfim energy launch");
@@ -717,27 +723,23 @@ static int apply_tfim_t(const void *state, void *out, int n, double J, double h,
     a.h = h;
     typedef TfimShape<C> S;
     constexpr int LS = S::L;
-    const int L0 = n < LS ? n : LS;
     const std::vector<TfimSweep> sw = tfim_sweeps<C>(a);
-    static int per_cu[2] = {0, 0};   // resident workgroups (the fewest of the kernels used)
-    int &pc = per_cu[sizeof(C) == 8 ? 0 : 1];
-    if (pc == 0) {
-        int b0 = 0, b1 = 0, b2 = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, k_apply_tfim_sweep<C, 0, 0, false>, S::RT, 0) != hipSuccess) b0 = 1;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_apply_tfim_sweep<C, LS, 0, true>, S::RT, 0) != hipSuccess) b1 = 1;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_apply_tfim_sweep<C, LS, 6, false>, S::RT, 0) != hipSuccess) b2 = 1;
-        pc = std::max(1, std::min(b0, std::min(b1, b2)));
+    static int per_cu[2][3] = {{0, 0, 0}, {0, 0, 0}};   // resident workgroups: [dtype][generic, first, later]
+    int *pc = per_cu[sizeof(C) == 8 ? 0 : 1];
+    if (pc[0] == 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc[0], k_apply_tfim_sweep<C, 0, 0, false>, S::RT, 0) != hipSuccess) pc[0] = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc[1], k_apply_tfim_sweep<C, S::L0, 0, true>, S::RT, 0) != hipSuccess) pc[1] = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc[2], k_apply_tfim_sweep<C, LS, 6, false>, S::RT, 0) != hipSuccess) pc[2] = 1;
+        for (int i = 0; i < 3; ++i) pc[i] = std::max(1, pc[i]);
     }
-    uint64_t g = a.N >> L0;
-    const uint64_t cap = (uint64_t)device_sm_count() * pc;
-    if (g > cap) g = cap;
-    const dim3 G((unsigned)g), B(S::RT);
     const C *ps = (const C *)state;
     C *po = (C *)out;
     for (const TfimSweep &w : sw) {   // in stream order: each later sweep adds to what the one before wrote
-        if (w.L == LS && w.xfrom == 0 && w.zz) hipLaunchKernelGGL((k_apply_tfim_sweep<C, LS, 0, true>), G, B, 0, s, ps, po, w);
-        else if (w.L == LS && !w.zz && w.xfrom >= 6 && w.xfrom < LS)
-            launch_later_apply<C, LS, LS - 1>(w.xfrom, G, B, s, ps, po, w);
+        const int kind = (w.L == S::L0 && w.xfrom == 0 && w.zz) ? 1 : (w.L == LS && !w.zz && w.xfrom >= 6 && w.xfrom < LS) ? 2 : 0;
+        const uint64_t g = std::min<uint64_t>(a.N >> w.L, (uint64_t)device_sm_count() * pc[kind]);
+        const dim3 G((unsigned)g), B(S::RT);
+        if (kind == 1) hipLaunchKernelGGL((k_apply_tfim_sweep<C, S::L0, 0, true>), G, B, 0, s, ps, po, w);
+        else if (kind == 2) launch_later_apply<C, LS, LS - 1>(w.xfrom, G, B, s, ps, po, w);
         else hipLaunchKernelGGL((k_apply_tfim_sweep<C, 0, 0, false>), G, B, 0, s, ps, po, w);
     }
     QSV_HIP_CHECK(hipGetLastError());

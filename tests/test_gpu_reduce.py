@@ -58,14 +58,14 @@ def test_probabilities_ghz(gpu):
 
 
 @pytest.mark.parametrize("dt", ["c64", "c128"])
-@pytest.mark.parametrize("n", [2, 3, 9, 15, 18, 20, 21, 23])
+@pytest.mark.parametrize("n", [2, 3, 9, 12, 13, 15, 18, 19, 21, 23])
 @pytest.mark.parametrize("periodic", [False, True])
 def test_tfim_energy_and_apply(gpu, dt, n, periodic):
-    """The energy's sweeps (complex64: bits 0..12, then 0..5 with 7 new bits
-    per sweep; complex128: 0..11, then 0..5 with 6 new) at sizes with one
-    sweep (2, 3, 9), with a last sweep that carries bits an earlier sweep
-    summed (15, 21, 23; 18 and 20 for complex128) and with only full later
-    sweeps (20 for complex64, 18 for complex128)."""
+    """The energy's and H psi's sweeps (bits 0..11 first; then bits 0..5
+    with 7 new bits per sweep for complex64, 6 for complex128) at sizes with
+    one sweep (2, 3, 9, 12), with a last sweep that carries bits an earlier
+    sweep summed (13, 15, 21, 23; 19 for complex128) and with only full later
+    sweeps (19 for complex64, 18 for complex128)."""
     import torch
     psi = _as_stored(W.random_state(n, 4), dt)
     d = _dev(psi, dt)
