@@ -887,20 +887,22 @@ int build_passes_once(qsv_plan *p, int local_bits, bool allow_fold) {
             out = sl;
             return __builtin_popcountll(sl) == size && (sl & ((1ull << lanes) - 1ull)) == (1ull << lanes) - 1ull;
         };
-        // (at most 13 local bits when the involution moves a lane bit, which
+        // (13 local bits first when the involution moves a lane bit, which
         // takes an LDS exchange: the pass has no gates to amortise, and a
         // 64 KiB chunk (complex64) lets two workgroups share a CU, so one's
         // loads overlap the other's exchange and stores -- measured on the
         // 30-qubit swap of qubits 0..5 with 24..29: 3.06 ms at 13 bits, 3.25
-        // at 14, 3.47 at 12; without an exchange the largest chunk streams
-        // best)
+        // at 14, 3.47 at 12.  An involution without fixed points, such as the
+        // reversal of an even number of qubits, has no closed set of 13
+        // bits; there 14 bits beat 12 (the 30-qubit reversal: 3.26 ms
+        // against 3.37).  Without an exchange the largest chunk streams best.)
         bool moves_lanes = false;
         for (int b = 0; b < lanes; ++b)
             if (t[b] != b) moves_lanes = true;
         uint64_t Sp = 0;
         int rbp = -1;
         const int l13 = std::min(L, 13);
-        const int order[4] = {moves_lanes ? l13 : L, moves_lanes ? l13 - 1 : L - 1, moves_lanes ? L : l13,
+        const int order[4] = {moves_lanes ? l13 : L, moves_lanes ? L : L - 1, moves_lanes ? l13 - 1 : l13,
                               moves_lanes ? L - 1 : l13 - 1};
         for (int size : order) {
             if (size - TB < 1 || rbp >= 0) continue;
