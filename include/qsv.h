@@ -324,7 +324,8 @@ int qsv_inner(const void *a, const void *b, int n, int dtype, double *out_dev, v
  * or periodic when `periodic` != 0 and n > 2). */
 int qsv_expval_zz_x(const void *state, int n, int dtype, double J, double h, int periodic,
                     double *out_dev, void *stream);
-/* out = (J sum Z_i Z_{i+1} + h sum X_i) psi, out a separate device state. */
+/* out = (J sum Z_i Z_{i+1} + h sum X_i) psi, out a separate device state
+ * (QSV_ERR_ARG when the two ranges overlap). */
 int qsv_apply_tfim(const void *state, void *out, int n, int dtype, double J, double h,
                    int periodic, void *stream);
 

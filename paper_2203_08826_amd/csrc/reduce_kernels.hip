@@ -822,7 +822,11 @@ int qsv_apply_tfim(const void *state, void *out, int n, int dtype, double J, dou
     int st = check_red(state, n, dtype, out);
     if (st) return st;
     if (((uintptr_t)out & 15) != 0) return fail(QSV_ERR_ALIGN, "out must be 16-byte aligned");
-    if (out == state) return fail(QSV_ERR_ARG, "out must not alias state");
+    {   // out is written while state is still read: the two must not overlap
+        const uintptr_t a = (uintptr_t)state, b = (uintptr_t)out;
+        const uintptr_t bytes = (uintptr_t)(dtype == QSV_C64 ? 8 : 16) << n;
+        if (a < b + bytes && b < a + bytes) return fail(QSV_ERR_ARG, "out must not overlap state");
+    }
     return dtype == QSV_C64 ? apply_tfim_t<float2>(state, out, n, J, h, periodic, (hipStream_t)stream)
                             : apply_tfim_t<double2>(state, out, n, J, h, periodic, (hipStream_t)stream);
 }

@@ -359,3 +359,15 @@ def test_compiled_exchanges_realise_their_partitions(dt):
     assert checked >= 4
     if dt == qsv.QSV_C64:
         assert split_seen >= 1
+
+
+def test_apply_tfim_rejects_overlapping_states_on_the_host():
+    """H psi writes out while it still reads state: overlapping ranges are
+    refused before anything is queued (no device is touched)."""
+    import ctypes
+    lib = qsv.load()
+    base = 1 << 20   # an aligned address; never dereferenced
+    for off in (0, 64, -64):
+        st = lib.qsv_apply_tfim(ctypes.c_void_p(base), ctypes.c_void_p(base + off * 8), 10, qsv.QSV_C64,
+                                ctypes.c_double(1.0), ctypes.c_double(0.5), 0, None)
+        assert st == -10, (off, st)   # QSV_ERR_ARG
