@@ -301,7 +301,8 @@ int qsv_sliced_run(void *host_state, int n, int dtype, const qsv_gate *gates, in
 
 /* Measurement probabilities of r qubits (methodology section: measurement):
  * out[m] = sum of |psi_i|^2 over i whose measured bits spell m, with
- * m = sum_j bit(i, qubits[j]) 2^(r-1-j).  out_dev holds 2^r doubles.
+ * m = sum_j bit(i, qubits[j]) 2^(r-1-j).  out_dev holds 2^r doubles and must
+ * not overlap the state (QSV_ERR_ARG).
  * 1 <= r <= n. */
 int qsv_probabilities(const void *state, int n, int dtype, const int *qubits, int r,
                       double *out_dev, void *stream);
@@ -340,7 +341,8 @@ int qsv_apply_tfim(const void *state, void *out, int n, int dtype, double J, dou
 /* Collapse onto outcome m of the r measured qubits, in place:
  * psi_i <- psi_i / sqrt(p) where the measured bits of i spell m, 0 elsewhere,
  * with p = ||P_m psi||^2 summed in float64 in a fixed order.  When p = 0 every
- * amplitude becomes 0.  prob_dev (device, may be NULL) receives p.
+ * amplitude becomes 0.  prob_dev (device, may be NULL) receives p; it must
+ * not lie inside the state (QSV_ERR_ARG).
  * 1 <= r <= n, m < 2^r (else QSV_ERR_ARG). */
 int qsv_collapse(void *state, int n, int dtype, const int *qubits, int r, uint64_t outcome,
                  double *prob_dev, void *stream);
@@ -404,7 +406,7 @@ int qsv_dm_probabilities(const void *rho, int n, int dtype, const int *qubits, i
  * the call computes Im <lam|P|psi> and then applies U^dagger to both vectors;
  * on return psi holds psi_0 (up to rounding).  grad_dev receives one double
  * per rotation, in circuit order.  The gates must be the ones that produced
- * psi. */
+ * psi; psi and lam are separate states (QSV_ERR_ARG when they overlap). */
 int qsv_adjoint_grad(void *psi, void *lam, int n, int dtype, const qsv_gate *gates, int ngates,
                      double *grad_dev, void *stream);
 

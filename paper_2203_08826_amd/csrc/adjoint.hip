@@ -170,7 +170,10 @@ extern "C" int qsv_adjoint_grad(void *psi, void *lam, int n, int dtype, const qs
     int st = validate_common(n, dtype, nullptr, 0, nullptr, 0);
     if (st) return st;
     if (!psi || !lam || (ngates > 0 && !gates)) return fail(QSV_ERR_NULL, "NULL argument");
-    if (psi == lam) return fail(QSV_ERR_ARG, "psi and lam must be distinct buffers");
+    {
+        const uint64_t bytes = (uint64_t)(dtype == QSV_C64 ? 8 : 16) << n;
+        if (ranges_overlap(psi, bytes, lam, bytes)) return fail(QSV_ERR_ARG, "psi and lam must not overlap");
+    }
     if (((uintptr_t)psi & 15) || ((uintptr_t)lam & 15)) return fail(QSV_ERR_ALIGN, "states must be 16-byte aligned");
     int nparams = 0;
     for (int i = 0; i < ngates; ++i) {

@@ -312,6 +312,8 @@ int qsv_collapse(void *state, int n, int dtype, const int *qubits, int r, uint64
         seen |= 1ull << qubits[j];
     }
     if (r < 64 && (outcome >> r) != 0) return fail(QSV_ERR_ARG, "outcome has bits above the measured qubits");
+    if (prob_dev && ranges_overlap(state, (uint64_t)(dtype == QSV_C64 ? 8 : 16) << n, prob_dev, sizeof(double)))
+        return fail(QSV_ERR_ARG, "prob_dev must not overlap the state");
     return dtype == QSV_C64 ? collapse_t<float2>(state, n, qubits, r, outcome, prob_dev, (hipStream_t)stream)
                             : collapse_t<double2>(state, n, qubits, r, outcome, prob_dev, (hipStream_t)stream);
 }

@@ -28,6 +28,13 @@ hipError_t dev_malloc_async(void **p, size_t bytes, hipStream_t s);
 hipError_t dev_free(void *p);
 hipError_t dev_free_async(void *p, hipStream_t s);
 
+// Whether the byte ranges [a, a + na) and [b, b + nb) share a byte (an output
+// that a kernel writes while it still reads an input must not).
+inline bool ranges_overlap(const void *a, uint64_t na, const void *b, uint64_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
 #define QSV_HIP_CHECK(expr)                                   \
     do {                                                      \
         hipError_t e_ = (expr);                               \

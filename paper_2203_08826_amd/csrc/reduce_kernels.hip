@@ -781,6 +781,8 @@ int qsv_probabilities(const void *state, int n, int dtype, const int *qubits, in
     if (st) return st;
     if (r < 1 || r > n) return fail(QSV_ERR_ARITY, "number of measured qubits must be in [1, n]");
     if (!qubits) return fail(QSV_ERR_NULL, "qubits is NULL");
+    if (ranges_overlap(state, (uint64_t)(dtype == QSV_C64 ? 8 : 16) << n, out_dev, (uint64_t)8 << r))
+        return fail(QSV_ERR_ARG, "out_dev must not overlap the state");
     uint64_t seen = 0;
     for (int j = 0; j < r; ++j) {
         if (qubits[j] < 0 || qubits[j] >= n) return fail(QSV_ERR_QUBIT_RANGE, "measured qubit out of range");
@@ -797,6 +799,8 @@ int qsv_probabilities_noalloc(const void *state, int n, int dtype, const int *qu
     if (st) return st;
     if (r < 1 || r > n) return fail(QSV_ERR_ARITY, "number of measured qubits must be in [1, n]");
     if (!qubits) return fail(QSV_ERR_NULL, "qubits is NULL");
+    if (ranges_overlap(state, (uint64_t)(dtype == QSV_C64 ? 8 : 16) << n, out_dev, (uint64_t)8 << r))
+        return fail(QSV_ERR_ARG, "out_dev must not overlap the state");
     uint64_t seen = 0;
     for (int j = 0; j < r; ++j) {
         if (qubits[j] < 0 || qubits[j] >= n) return fail(QSV_ERR_QUBIT_RANGE, "measured qubit out of range");
@@ -822,11 +826,8 @@ int qsv_apply_tfim(const void *state, void *out, int n, int dtype, double J, dou
     int st = check_red(state, n, dtype, out);
     if (st) return st;
     if (((uintptr_t)out & 15) != 0) return fail(QSV_ERR_ALIGN, "out must be 16-byte aligned");
-    {   // out is written while state is still read: the two must not overlap
-        const uintptr_t a = (uintptr_t)state, b = (uintptr_t)out;
-        const uintptr_t bytes = (uintptr_t)(dtype == QSV_C64 ? 8 : 16) << n;
-        if (a < b + bytes && b < a + bytes) return fail(QSV_ERR_ARG, "out must not overlap state");
-    }
+    const uint64_t bytes = (uint64_t)(dtype == QSV_C64 ? 8 : 16) << n;
+    if (ranges_overlap(state, bytes, out, bytes)) return fail(QSV_ERR_ARG, "out must not overlap state");
     return dtype == QSV_C64 ? apply_tfim_t<float2>(state, out, n, J, h, periodic, (hipStream_t)stream)
                             : apply_tfim_t<double2>(state, out, n, J, h, periodic, (hipStream_t)stream);
 }

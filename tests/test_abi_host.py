@@ -371,3 +371,23 @@ def test_apply_tfim_rejects_overlapping_states_on_the_host():
         st = lib.qsv_apply_tfim(ctypes.c_void_p(base), ctypes.c_void_p(base + off * 8), 10, qsv.QSV_C64,
                                 ctypes.c_double(1.0), ctypes.c_double(0.5), 0, None)
         assert st == -10, (off, st)   # QSV_ERR_ARG
+
+
+def test_outputs_overlapping_their_inputs_are_refused_on_the_host():
+    """Probabilities, collapse and the adjoint write device outputs while they
+    still read the state: an output range inside the state is refused before
+    anything is queued (fake, never dereferenced addresses)."""
+    import ctypes
+    lib = qsv.load()
+    base = 1 << 20
+    n = 10
+    qs = (ctypes.c_int * 2)(0, 3)
+    for fn in (lib.qsv_probabilities, lib.qsv_probabilities_noalloc):
+        st = fn(ctypes.c_void_p(base), n, qsv.QSV_C64, qs, 2, ctypes.c_void_p(base + 4096), None)
+        assert st == -10, st
+    st = lib.qsv_collapse(ctypes.c_void_p(base), n, qsv.QSV_C128, qs, 2, ctypes.c_uint64(1),
+                          ctypes.c_void_p(base + 16 * 1023), None)
+    assert st == -10, st
+    st = lib.qsv_adjoint_grad(ctypes.c_void_p(base), ctypes.c_void_p(base + 8 * 512), n, qsv.QSV_C64, None, 0,
+                              None, None)
+    assert st == -10, st
