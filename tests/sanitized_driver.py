@@ -2,7 +2,8 @@
 Sanitizer build (run by test_sanitized_host.py in a child process with the
 sanitizer runtime preloaded and QSV_LIBRARY naming that build).
 
-Everything here stays on the host: argument validation and its error paths,
+Everything here stays on the host: argument validation and its error paths
+(overlapping output ranges among them),
 group enumeration, gate matrices, and plan creation in every mode that needs
 no device (per-gate, greedy fusion with and without matrix-core blocks, LDS
 passes interpreted and compiled, the density-matrix doubling), with every
@@ -89,6 +90,19 @@ def main():
         read_back(p)
         count += 1
     rng.standard_normal(1)
+    # outputs overlapping the state they are computed from: refused before any
+    # device work (fake, never dereferenced addresses)
+    import ctypes
+    lib = qsv.load()
+    base = 1 << 20
+    qs = (ctypes.c_int * 2)(0, 3)
+    assert lib.qsv_apply_tfim(ctypes.c_void_p(base), ctypes.c_void_p(base + 512), 10, qsv.QSV_C64,
+                              ctypes.c_double(1.0), ctypes.c_double(0.5), 0, None) == -10
+    assert lib.qsv_probabilities(ctypes.c_void_p(base), 10, qsv.QSV_C64, qs, 2, ctypes.c_void_p(base + 4096), None) == -10
+    assert lib.qsv_collapse(ctypes.c_void_p(base), 10, qsv.QSV_C128, qs, 2, ctypes.c_uint64(1),
+                            ctypes.c_void_p(base + 16 * 1023), None) == -10
+    assert lib.qsv_adjoint_grad(ctypes.c_void_p(base), ctypes.c_void_p(base + 4096), 10, qsv.QSV_C64, None, 0,
+                                None, None) == -10
     print("sanitized host workout: %d plans" % count, flush=True)
 
 
